@@ -1,0 +1,285 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and the mathematics.
+
+P1  one raster ICD pass == the closed form of eq. (ICDUpdate1)
+P2  MACE fixed point == dense Cholesky MAP (quadratic prior; MAP equivalence of
+    the MACE equations, Sec. II-B); q-GGMRF: == centralised exact ICD and the
+    gradient of f vanishes (checked by finite differences of f)
+P3  invariants at the fixed point: X_i = mean(w) (proof of Theorem 1), one more
+    pass is a no-op (Lemma B.1), exact prox of v_i returns x*, u_i sums to 0
+P4  the agent cost never increases during a pass (both coordinate rules)
+P5  partial-update MACE == the exact augmented linear map of Theorem 2; its
+    limit is the map's fixed point
+P6  special cases: N = 1, q-GGMRF limits (p = q, T -> inf, large |d|)
+plus the divergence of Algorithm 1 at sigma = 0.05 on the 64x64 workload.
+"""
+import numpy as np
+import pytest
+
+import mace_inputs as mi
+import oracle
+from tests import dense_ref as dr
+
+
+def _problem(geom, seed, N, kind=0, sx=0.001, p=2.0, q=2.0, T=1.0):
+    cp, row, val = mi.system_matrix(geom)
+    s = mi.scan(geom, seed)
+    va = mi.interleaved_partition(geom.n_views, N)
+    O = oracle.Oracle(geom.nx, geom.ny, geom.n_views, geom.n_channels, cp, row, val, s.y, s.lam,
+                      va, kind, sx, p, q, T)
+    A = dr.dense_A(geom, cp, row, val)
+    return O, A, s.lam.astype(np.float64), s.y.astype(np.float64), va
+
+
+# ---------------- P1 ----------------
+@pytest.mark.parametrize("N,agent", [(1, 0), (3, 1)])
+def test_P1_icd_pass_equals_gauss_seidel_closed_form(N, agent):
+    g = mi.Geometry(8, 8, 12, 12)
+    sx, sigma = 0.01, 0.02
+    O, A, lam, y, va = _problem(g, 21, N, 0, sx)
+    Lb = dr.laplacian(g.nx, g.ny)
+    Hs, bs = dr.agent_system(g, A, lam, y, Lb, sx, va, N)
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 0.05, g.n)
+    v = rng.uniform(0, 0.05, g.n)
+    z = x.copy()
+    e = O.error_sinogram(x, agent=agent)
+    O.icd_pass(agent, sigma, v, z, e)
+    ref = dr.icd_pass_closed_form(Hs[agent], bs[agent], x, v, sigma)
+    np.testing.assert_allclose(z, ref, rtol=1e-11, atol=1e-14)
+    # the kept error sinogram equals y - A z on the agent's rows
+    r = dr.agent_rows(g, va, agent)
+    np.testing.assert_allclose(e[r], y[r] - A[r] @ z, atol=1e-10)
+
+
+def test_P1_visiting_order_is_respected():
+    g = mi.Geometry(8, 8, 12, 12)
+    O, A, lam, y, va = _problem(g, 22, 2, 0, 0.01)
+    Lb = dr.laplacian(g.nx, g.ny)
+    Hs, bs = dr.agent_system(g, A, lam, y, Lb, 0.01, va, 2)
+    perm = np.random.default_rng(1).permutation(g.n)
+    x = np.full(g.n, 0.01)
+    v = np.full(g.n, 0.02)
+    z = x.copy()
+    e = O.error_sinogram(x, agent=0)
+    O.icd_pass(0, 0.05, v, z, e, order=perm)
+    # Gauss-Seidel in the permuted order == closed form on the permuted system
+    Hp = Hs[0][np.ix_(perm, perm)]
+    ref = dr.icd_pass_closed_form(Hp, bs[0][perm], x[perm], v[perm], 0.05)
+    np.testing.assert_allclose(z[perm], ref, rtol=1e-11, atol=1e-14)
+
+
+# ---------------- P2 / P3 ----------------
+@pytest.fixture(scope="module")
+def quad32():
+    g = mi.Geometry(32, 32, 64, 48)
+    N, sx, sigma, rho = 4, 0.001, 0.001, 0.8
+    O, A, lam, y, va = _problem(g, 7, N, 0, sx)
+    Lb = dr.laplacian(g.nx, g.ny)
+    xmap = dr.map_quadratic(A, lam, y, Lb, sx)
+    res = O.mace_solve(rho, sigma, 5000, tol=1e-13)
+    return dict(g=g, N=N, sx=sx, sigma=sigma, rho=rho, O=O, A=A, lam=lam, y=y, va=va,
+                Lb=Lb, xmap=xmap, res=res)
+
+
+def test_P2_mace_fixed_point_is_the_map(quad32):
+    r, xmap = quad32["res"], quad32["xmap"]
+    assert r["resid"][-1] < 1e-13
+    nrmse = np.linalg.norm(r["x"] - xmap) / np.linalg.norm(xmap)
+    assert nrmse < 1e-9, nrmse
+
+
+def test_P3_fixed_point_invariants(quad32):
+    d = quad32
+    O, r, N, sigma = d["O"], d["res"], d["N"], d["sigma"]
+    x = r["x"]
+    w = r["w"]
+    # X* = G w*: every agent state equals the consensus
+    assert np.abs(r["X"] - x[None, :]).max() < 1e-11 * np.abs(x).max()
+    wbar = w.mean(axis=0)
+    np.testing.assert_allclose(wbar, x, rtol=0, atol=1e-15)
+    grads = []
+    for i in range(N):
+        v = 2.0 * wbar - w[i]
+        # Lemma B.1: one more partial update leaves the fixed point unchanged
+        z = x.copy()
+        e = O.error_sinogram(x, agent=i)
+        O.icd_pass(i, sigma, v, z, e)
+        assert np.abs(z - x).max() < 1e-10 * np.abs(x).max()
+        # F_i(v_i*) = x*: the exact proximal map returns the consensus
+        zp, _ = O.prox(i, sigma, v, z0=x, rtol=1e-15, max_passes=200)
+        assert np.abs(zp - x).max() < 1e-10 * np.abs(x).max()
+        # sigma^2 grad f_i(x*) = v_i* - x*
+        gi = O.gradient(x, agent=i)
+        np.testing.assert_allclose(sigma ** 2 * gi, v - x, atol=1e-9 * np.abs(x).max())
+        grads.append(gi)
+    # the agents' forces balance: sum_i grad f_i(x*) = grad f(x*) = 0
+    gsum = np.sum(grads, axis=0)
+    scale = np.abs(grads).max()
+    assert np.abs(gsum).max() < 1e-8 * scale
+
+
+def test_P2_qggmrf_fixed_point_matches_centralised_icd():
+    g = mi.Geometry(24, 24, 48, 36)
+    N, sx, sigma = 2, 0.001, 0.001
+    O, A, lam, y, va = _problem(g, 9, N, 1, sx, 2.0, 1.2, 1.0)
+    res = O.mace_solve(0.8, sigma, 6000, tol=1e-13, mode=oracle.MODE_SURROGATE)
+    assert res["resid"][-1] < 1e-13
+    xc, it = O.centralized_icd(rtol=1e-15, max_passes=20000, mode=oracle.MODE_EXACT)
+    nrmse = np.linalg.norm(res["x"] - xc) / np.linalg.norm(xc)
+    assert nrmse < 1e-8, nrmse
+    # grad f(x*) = 0: central finite differences of the oracle's cost f
+    rng = np.random.default_rng(3)
+    x = res["x"]
+    for s in rng.choice(g.n, 6, replace=False):
+        h = 1e-7
+        xp, xm = x.copy(), x.copy()
+        xp[s] += h
+        xm[s] -= h
+        fd = (O.cost(xp) - O.cost(xm)) / (2 * h)
+        gs = O.gradient(x)[s]
+        # the gradient routine agrees with the cost ...
+        assert abs(fd - gs) < 1e-4 * (abs(O.cost(x)) / np.abs(x).max() + 1)
+        # ... and vanishes at the fixed point relative to its scale at x = 0
+    g0 = np.abs(O.gradient(np.zeros(g.n))).max()
+    assert np.abs(O.gradient(x)).max() < 1e-8 * g0
+    # strict convexity: random perturbations never lower f
+    f0 = O.cost(x)
+    for _ in range(5):
+        assert O.cost(x + 1e-4 * rng.standard_normal(g.n)) > f0
+
+
+# ---------------- P4 ----------------
+@pytest.mark.parametrize("mode", [oracle.MODE_SURROGATE, oracle.MODE_EXACT])
+def test_P4_agent_cost_monotone_within_a_pass(mode):
+    g = mi.Geometry(10, 10, 16, 16)
+    O, A, lam, y, va = _problem(g, 31, 2, 1, 0.002, 2.0, 1.1, 1.0)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 0.1, g.n)
+    v = rng.uniform(0, 0.1, g.n)
+    z = x.copy()
+    e = O.error_sinogram(x, agent=1)
+    phi0 = O.cost(x, agent=1, v=v, sigma=0.01)
+    tr = O.icd_pass(1, 0.01, v, z, e, mode=mode, trace=True)
+    seq = np.concatenate([[phi0], tr])
+    assert np.all(np.diff(seq) <= 1e-12 * abs(phi0)), np.diff(seq).max()
+    assert seq[-1] < seq[0]
+
+
+def test_P4_exact_rule_solves_the_coordinate_problem():
+    # after an exact-rule update of pixel s, the partial derivative of the
+    # agent cost along s vanishes (finite differences of the cost)
+    g = mi.Geometry(8, 8, 12, 12)
+    O, A, lam, y, va = _problem(g, 32, 2, 1, 0.003, 2.0, 1.2, 1.0)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 0.1, g.n)
+    v = rng.uniform(0, 0.1, g.n)
+    z = x.copy()
+    e = O.error_sinogram(x, agent=0)
+    order = np.array([27], dtype=np.int64)
+    order = np.concatenate([order, np.full(g.n - 1, 27)])  # visit pixel 27 repeatedly
+    O.icd_pass(0, 0.02, v, z, e, order=order, mode=oracle.MODE_EXACT)
+    h = 1e-7
+    zp, zm = z.copy(), z.copy()
+    zp[27] += h
+    zm[27] -= h
+    d = (O.cost(zp, 0, v, 0.02) - O.cost(zm, 0, v, 0.02)) / (2 * h)
+    curv = (O.cost(zp, 0, v, 0.02) - 2 * O.cost(z, 0, v, 0.02) + O.cost(zm, 0, v, 0.02)) / h ** 2
+    assert abs(d) < 1e-5 * curv * max(abs(z[27]), 1e-3)
+
+
+# ---------------- P5 ----------------
+def test_P5_theorem2_linear_map():
+    g = mi.Geometry(8, 8, 16, 12)
+    N, sx, rho = 2, 0.003, 0.8
+    O, A, lam, y, va = _problem(g, 5, N, 0, sx)
+    Lb = dr.laplacian(g.nx, g.ny)
+    Hs, bs = dr.agent_system(g, A, lam, y, Lb, sx, va, N)
+    sigma = 0.002
+    M, c = dr.pu_mace_linear_map(Hs, bs, sigma, rho)
+    # iterate the exact map from w = 0, X = G(0) = 0 and compare trajectories
+    z = np.zeros(2 * N * g.n)
+    for k in range(25):
+        z = M @ z + c
+    r = O.mace_solve(rho, sigma, 25)
+    np.testing.assert_allclose(r["w"].reshape(-1), z[:N * g.n], rtol=1e-9, atol=1e-13)
+    np.testing.assert_allclose(r["X"].reshape(-1), z[N * g.n:], rtol=1e-9, atol=1e-13)
+    # small sigma: spectral radius < 1, the oracle reaches the map's fixed point
+    srad = np.abs(np.linalg.eigvals(M)).max()
+    assert srad < 1.0
+    zfix = np.linalg.solve(np.eye(M.shape[0]) - M, c)
+    r = O.mace_solve(rho, sigma, 20000, tol=1e-14)
+    np.testing.assert_allclose(r["w"].reshape(-1), zfix[:N * g.n], rtol=1e-8,
+                               atol=1e-10 * np.abs(zfix).max())
+
+
+def test_configured_sigma_diverges_on_64x64():
+    """At sigma = 0.05 (sigma^2 theta2 >> 1) Algorithm 1 does not converge on the
+    64x64 4-agent workload: the exact linear map of Theorem 2 for the same
+    problem class has spectral radius > 1, and the oracle's iterates grow."""
+    w = mi.WORKLOADS["plain64"]
+    g = w.geom
+    O, A, lam, y, va = _problem(g, w.seed, w.n_agents, 0, w.sigma_x)
+    r = O.mace_solve(w.rho, w.sigma, 1200)
+    assert not np.all(np.isfinite(r["x"])) or np.abs(r["x"]).max() > 1e3
+    # a stable setting (small sigma) stays bounded on the same data
+    r2 = O.mace_solve(w.rho, 2.5e-4, 300)
+    assert np.abs(r2["x"]).max() < 1.0
+    # the small analogue: 12x12, 4 agents, same prior and sigma
+    gs = mi.Geometry(12, 12, 24, 18)
+    O2, A2, lam2, y2, va2 = _problem(gs, 5, 4, 0, w.sigma_x)
+    Hs, bs = dr.agent_system(gs, A2, lam2, y2, dr.laplacian(12, 12), w.sigma_x, va2, 4)
+    M, _ = dr.pu_mace_linear_map(Hs, bs, w.sigma, w.rho)
+    assert np.abs(np.linalg.eigvals(M)).max() > 1.0
+
+
+# ---------------- P6 ----------------
+def test_P6_single_agent_reaches_centralised_map():
+    g = mi.Geometry(16, 16, 32, 24)
+    sx = 0.002
+    O, A, lam, y, va = _problem(g, 13, 1, 0, sx)
+    xmap = dr.map_quadratic(A, lam, y, dr.laplacian(16, 16), sx)
+    r = O.mace_solve(0.8, 0.01, 20000, tol=1e-13)
+    assert np.linalg.norm(r["x"] - xmap) / np.linalg.norm(xmap) < 1e-9
+    xc, _ = O.centralized_icd(rtol=1e-15, max_passes=50000)
+    assert np.linalg.norm(xc - xmap) / np.linalg.norm(xmap) < 1e-9
+
+
+def test_P6_reflection_is_an_involution():
+    rng = np.random.default_rng(6)
+    N, n = 5, 7
+    w = rng.standard_normal((N, n))
+    refl = lambda u: 2 * u.mean(axis=0)[None, :] - u
+    np.testing.assert_allclose(refl(refl(w)), w, atol=1e-14)
+
+
+def test_P6_qggmrf_special_cases():
+    g = mi.Geometry(8, 8, 12, 12)
+    rng = np.random.default_rng(8)
+    x = rng.uniform(0, 0.05, g.n)
+    sx = 0.01
+    Oq, *_ = _problem(g, 1, 1, 0, sx)
+    # T -> infinity: q-GGMRF equals the quadratic prior
+    Ot, *_ = _problem(g, 1, 1, 1, sx, 2.0, 1.2, 1e20)
+    assert abs(Ot.prior(x) - Oq.prior(x)) < 1e-10 * Oq.prior(x)
+    # p = q: rho(d) = |d|^p / (2 p sigma_x^p), half the quadratic for p = 2
+    Op, *_ = _problem(g, 1, 1, 1, sx, 2.0, 2.0, 1.0)
+    assert abs(Op.prior(x) - 0.5 * Oq.prior(x)) < 1e-12 * Oq.prior(x)
+    # one clique, large difference: rho ~ |d|^q T^(p-q) / (p sigma_x^q)
+    g2 = mi.Geometry(2, 1, 2, 4)
+    O2, *_ = _problem(g2, 1, 1, 1, sx, 2.0, 1.2, 1.0)
+    d = 1e4 * sx
+    val = O2.prior(np.array([d, 0.0]))
+    asym = mi.B_EDGE * d ** 1.2 / (2.0 * sx ** 1.2)
+    assert abs(val / asym - 1.0) < 1e-2
+    # small difference: quadratic with curvature 1/sigma_x^2
+    d = 1e-6 * sx
+    val = O2.prior(np.array([d, 0.0]))
+    assert abs(val / (mi.B_EDGE * d * d / (2 * sx * sx)) - 1.0) < 1e-3
+
+
+def test_P8_oracle_is_deterministic():
+    g = mi.Geometry(16, 16, 24, 24)
+    O, *_ = _problem(g, 2, 3, 1, 0.003, 2.0, 1.2, 1.0)
+    a = O.mace_solve(0.8, 0.003, 20)
+    b = O.mace_solve(0.8, 0.003, 20)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["resid"], b["resid"])
