@@ -1,0 +1,195 @@
+/*
+ * mace.h -- C ABI of the MI355X partial-update MACE CT reconstruction library.
+ *
+ * The library computes the MAP image
+ *     x* = argmin_x  sum_k 1/2 ||y_k - A_k x||^2_{Lambda_k} + h(x)
+ * (Sec. II-A, eq. (MAPest) and eq. (global_obj)) by partial-update multi-agent
+ * consensus equilibrium: the views are split into N agents (view subsets J_i,
+ * Sec. II-A), each agent applies one ICD pass as a partial proximal update of
+ *     f_i(x) = sum_{k in J_i} 1/2 ||y_k - A_k x||^2_{Lambda_k} + h(x)/N
+ * (eq. (local_obj), eq. (prox_F), Algorithm 2), and the agents are tied
+ * together by the consensus average G (eq. (G_operators)) and the Mann
+ * iteration w <- rho (2F - I)(2G - I) w + (1 - rho) w (eq. (Mann), Algorithm 1).
+ * The returned image is the mean of the agents' w (Algorithm 1, "Solution").
+ *
+ * Conventions
+ *   - Image: nx * ny pixels, raster order s = i * nx + j (row i, column j).
+ *   - Sinogram rows: r = view * n_channels + channel (view-major).
+ *   - A is given in compressed sparse columns (one column per pixel).  Within
+ *     one view a column may have at most two nonzeros, on adjacent channels
+ *     (true whenever the channel spacing is at least the pixel width over
+ *     sqrt(2), e.g. 1 mm pixels and 1 mm channels).
+ *   - Units are the caller's (e.g. A in mm, x in 1/mm).
+ *   - Every int-returning call returns MACE_OK (0), a negative error code, or
+ *     a positive warning; mace_last_error() describes the last failure of the
+ *     calling thread.
+ *   - All host pointers are read only during the call and stay owned by the
+ *     caller; outputs go to caller buffers.  A mace_system owns its device
+ *     memory until mace_free_system().  Calls on one mace_system must not
+ *     overlap (the system holds one scan workspace).
+ *   - Device-pointer variants (suffix _dev) take device addresses and a HIP
+ *     stream (hipStream_t passed as void*, NULL = default stream); they
+ *     enqueue work on that stream and return after it has finished.
+ */
+#ifndef MACE_H
+#define MACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MACE_OK 0
+#define MACE_E_ARG (-1)       /* invalid argument */
+#define MACE_E_MATRIX (-2)    /* malformed or unsupported system matrix */
+#define MACE_E_PARTITION (-3) /* view_to_agent is not a partition */
+#define MACE_E_NOMEM (-4)     /* device or host memory exhausted */
+#define MACE_E_HIP (-5)       /* HIP runtime error */
+#define MACE_E_NONFINITE (-6) /* the iteration produced a non-finite residual */
+#define MACE_W_MAXITER 1      /* max_iters reached before tol; x_out written */
+
+typedef struct mace_system mace_system;
+
+typedef struct {
+  int32_t nx, ny;       /* image size in pixels */
+  int32_t n_views;      /* number of views N_theta */
+  int32_t n_channels;   /* channels per view N_D */
+} mace_geom;
+
+/* Prior h(x) = sum over unordered 8-neighbour pairs {s,r} of b_sr rho(x_s-x_r),
+ * b_sr = b_edge for edge neighbours and b_diag for diagonal ones, free image
+ * boundary.  kind 0: rho(d) = d^2 / (2 sigma_x^2).  kind 1 (q-GGMRF):
+ * rho(d) = |d|^p / (p sigma_x^p) / (1 + (|d| / (T sigma_x))^(p-q)), which the
+ * GPU path supports for p = 2 and 1 <= q <= 2 (the ICD step uses the
+ * potential's symmetric quadratic majoriser, curvature rho'(d)/d, which is
+ * finite at d = 0 only for p = 2).  b_edge = b_diag = 0 selects the defaults
+ * 1/(4 + 2 sqrt 2) and 1/(4 sqrt 2 + 4), which sum to 1 over the 8 neighbours. */
+typedef struct {
+  int32_t kind;
+  double sigma_x, p, q, T;
+  double b_edge, b_diag;
+} mace_prior;
+
+/* Execution options (NULL = all defaults). */
+typedef struct {
+  int32_t precision;      /* 0: A values FP32 (default); 1: FP16 with a per
+                             (agent, pixel) FP32 scale */
+  int32_t sv_size;        /* super-voxel side S in pixels; 0 = default (4) */
+  int32_t rows_per_agent; /* concurrent super-voxels per agent; 0 = automatic;
+                             1 = sequential (one super-voxel of an agent at a
+                             time: the visiting order of mace_visit_order) */
+  int32_t fp32_tail_iters;/* with precision 1: last iterations in FP32 A */
+  int64_t hbm_budget_bytes; /* 0 = no limit */
+} mace_opts;
+
+typedef struct {
+  int32_t iters;    /* Mann iterations run */
+  double residual;  /* last r_k = ||X^{k+1} - G w^k|| / ||w^k|| (FP64) */
+  double equits;    /* sweeps * iters: agent-voxel updates / (N * n) */
+  int32_t status;   /* MACE_OK, MACE_W_MAXITER or MACE_E_NONFINITE */
+  double sweep_ms;  /* with timing on: time of the ICD sweep launches (HIP events) */
+  int32_t sweep_launches; /* number of sweep launches timed */
+  double iter_ms;   /* with timing on: time of all Mann iterations (HIP events) */
+} mace_info;
+
+/*
+ * Load (once per scanner geometry) the precomputed sparse system matrix and
+ * split its views into n_agents view subsets (Sec. I: the matrix is
+ * precomputed because the geometry is fixed; Sec. II-A: the partition).
+ *   col_ptr[nx*ny + 1] (int64, col_ptr[0] = 0, non-decreasing),
+ *   row_idx[nnz] (ascending and distinct within a column, < n_views*n_channels),
+ *   val[nnz] (finite).
+ *   view_to_agent[n_views]: agent of each view (NULL = interleaved, view k ->
+ *   agent k mod n_agents); every agent must own at least one view and at most
+ *   128 views.
+ * The matrix is copied and repacked on the device; *out receives the handle.
+ * Errors: MACE_E_ARG, MACE_E_MATRIX, MACE_E_PARTITION, MACE_E_NOMEM, MACE_E_HIP.
+ */
+int mace_load_system(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
+                     const float* val, int32_t n_agents, const int32_t* view_to_agent,
+                     const mace_opts* opts, mace_system** out);
+
+/*
+ * Partial-update MACE (Algorithm 1) with `sweeps` ICD passes per partial
+ * update (Algorithm 2).  y and lambda: [n_views * n_channels] measurements and
+ * diagonal inverse-variance weights (host).  rho in (0,1) (eq. (Mann)),
+ * sigma > 0 (eq. (prox_F)).  w_init: [n_agents * nx * ny] initial w (NULL =
+ * 0; the fixed point does not depend on it).  Stops after max_iters Mann
+ * iterations or when r_k < tol (tol <= 0: never); x_out[nx*ny] receives the
+ * consensus image mean_i w_i.  info (optional) receives the statistics.
+ * Returns MACE_OK, MACE_W_MAXITER (tol > 0 not reached), or an error.
+ */
+int mace_solve(mace_system* sys, const float* y, const float* lambda, const mace_prior* prior,
+               double rho, double sigma, int32_t sweeps, int32_t max_iters, double tol,
+               const float* w_init, float* x_out, mace_info* info);
+
+/* Device-pointer variant of mace_solve (all arrays in device memory). */
+int mace_solve_dev(mace_system* sys, const float* y, const float* lambda,
+                   const mace_prior* prior, double rho, double sigma, int32_t sweeps,
+                   int32_t max_iters, double tol, const float* w_init, float* x_out,
+                   mace_info* info, void* stream);
+
+/*
+ * Partial proximal update of one agent (Algorithm 2 applied `sweeps` times):
+ * starting from x_init, ICD passes on f_i(z) + ||z - v||^2/(2 sigma^2)
+ * (eq. (prox_F)); with many sweeps this approaches F_i(v).  All image arrays
+ * have nx*ny entries (host).
+ */
+int mace_prox(mace_system* sys, int32_t agent, const float* y, const float* lambda,
+              const mace_prior* prior, double sigma, const float* v, const float* x_init,
+              int32_t sweeps, float* x_out);
+
+/*
+ * Pixel visiting order of one ICD pass (int64[nx*ny]): super-voxel colour
+ * phases, the super-voxels of a phase in schedule order, raster order inside a
+ * super-voxel.  With rows_per_agent = 1 every agent visits pixels exactly in
+ * this order.
+ */
+int mace_visit_order(const mace_system* sys, int64_t* order);
+
+/* Stacked agent states of the last solve (device layout [N][nx*ny], copied to
+ * host): w and X (either may be NULL). */
+int mace_get_state(const mace_system* sys, float* w, float* X);
+
+/* Error sinogram e = y - A X_i of the last solve, every row from its own
+ * agent's state, copied to host in global row order (float[n_views*n_channels]). */
+int mace_get_error_sinogram(const mace_system* sys, float* e);
+
+/*
+ * Scale of every ICD coordinate step, gamma in (0, 1] (default 1): z_s +=
+ * gamma * alpha_s.  gamma = 1 is Algorithm 2's exact coordinate minimisation
+ * (of the prior's quadratic majoriser); gamma < 1 under-relaxes the partial
+ * update.  A pixel is left unchanged exactly when its coordinate derivative
+ * vanishes for any gamma, so the fixed points -- and, by Theorem 1, the MAP
+ * solution -- do not depend on it (the argument of Lemma B.1); it changes
+ * the iterates and their stability when many super-voxels of an agent are
+ * updated at once.  Applies to later mace_solve / mace_prox calls.
+ */
+int mace_set_relaxation(mace_system* sys, double gamma);
+
+/* Enable (1) or disable (0) HIP-event timing of the solve's kernels; the
+ * figures land in mace_info.sweep_ms / sweep_launches / iter_ms. */
+int mace_set_timing(mace_system* sys, int32_t enable);
+
+/* Bytes of repacked system matrix held on the device. */
+int64_t mace_system_bytes(const mace_system* sys);
+
+/*
+ * Host-only dry run of mace_load_system for the same arguments: builds the
+ * device tables and the super-voxel schedules in host memory and checks every
+ * index the kernels form from them (band rows, record rows, task ids, LDS
+ * size), without using a device.  *lds_bytes (optional) receives the LDS a
+ * workgroup of the main kernel needs.  Same error codes as mace_load_system.
+ */
+int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
+                      const float* val, int32_t n_agents, const int32_t* view_to_agent,
+                      const mace_opts* opts, int64_t* lds_bytes);
+
+void mace_free_system(mace_system* sys);
+const char* mace_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MACE_H */

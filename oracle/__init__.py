@@ -82,9 +82,9 @@ def _load():
         L.orc_cost.argtypes = [vp, i32, vp, vp, d]
         L.orc_cost.restype = d
         L.orc_gradient.argtypes = [vp, i32, vp, vp]
-        L.orc_icd_pass.argtypes = [vp, i32, d, vp, vp, vp, vp, i32, vp]
+        L.orc_icd_pass.argtypes = [vp, i32, d, vp, vp, vp, vp, i32, d, vp]
         L.orc_icd_pass.restype = i32
-        L.orc_mace_solve.argtypes = [vp, d, d, i32, i32, d, vp, vp, i32, vp, vp, vp]
+        L.orc_mace_solve.argtypes = [vp, d, d, i32, i32, d, vp, vp, i32, d, vp, vp, vp]
         L.orc_mace_solve.restype = i32
         L.orc_prox.argtypes = [vp, i32, d, vp, vp, i32, d, i32]
         L.orc_prox.restype = i32
@@ -168,20 +168,21 @@ class Oracle:
 
     # ---- Algorithm 2 ----
     def icd_pass(self, agent, sigma, v, z, e, order=None, mode=MODE_SURROGATE,
-                 trace=False):
-        """One ICD pass, in place on z (float64 [n]) and e (float64 [n_rows])."""
+                 trace=False, relax=1.0):
+        """One ICD pass, in place on z (float64 [n]) and e (float64 [n_rows]).
+        relax scales each coordinate step (1 = Algorithm 2)."""
         assert z.dtype == np.float64 and z.flags.c_contiguous
         assert e.dtype == np.float64 and e.flags.c_contiguous
         vd = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
         od = None if order is None else np.ascontiguousarray(order, dtype=np.int64)
         tr = np.empty(self.n) if trace else None
         _load().orc_icd_pass(self._h, int(agent), float(sigma), _p(vd), _p(z), _p(e), _p(od),
-                             int(mode), _p(tr))
+                             int(mode), float(relax), _p(tr))
         return tr
 
     # ---- Algorithm 1 ----
     def mace_solve(self, rho, sigma, max_iters, tol=0.0, sweeps=1, w_init=None, order=None,
-                   mode=MODE_SURROGATE):
+                   mode=MODE_SURROGATE, relax=1.0):
         """Returns dict(x, w, X, resid, iters)."""
         w = (np.zeros(self.N * self.n) if w_init is None
              else np.ascontiguousarray(w_init, dtype=np.float64).reshape(-1).copy())
@@ -191,7 +192,7 @@ class Oracle:
         od = None if order is None else np.ascontiguousarray(order, dtype=np.int64)
         k = _load().orc_mace_solve(self._h, float(rho), float(sigma), int(sweeps),
                                    int(max_iters), float(tol), _p(w), _p(od), int(mode),
-                                   _p(x), _p(X), _p(res))
+                                   float(relax), _p(x), _p(X), _p(res))
         return dict(x=x, w=w.reshape(self.N, self.n), X=X.reshape(self.N, self.n),
                     resid=res[:k], iters=int(k))
 

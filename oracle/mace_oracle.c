@@ -296,12 +296,16 @@ void orc_gradient(const orc_state* S, int agent, const double* x, double* g) {
  *   sum_{r in rows} 1/2 Lambda_r (y_r - (Az)_r)^2 + pscale*h(z)
  *     + ||z - v||^2/(2 sigma^2)          (prox term absent if sigma <= 0)
  * where pscale = 1/N for an agent and 1 for the centralised case.
+ * relax scales every coordinate step (z_s += relax * alpha_s); relax = 1 is
+ * the exact coordinate minimisation of Algorithm 2, relax in (0, 1) an
+ * under-relaxed pass with the same fixed points (alpha_s = 0 exactly when the
+ * coordinate derivative vanishes, whatever relax is).
  * z and e (= y - Az on the pass's rows, full-length array) are updated in
  * place.  If phi_trace is given, the cost after every update is stored there
  * (slow: full recomputation, small problems only).
  */
 int orc_icd_pass(const orc_state* S, int agent, double sigma, const double* v,
-                 double* z, double* e, const int64_t* order, int mode,
+                 double* z, double* e, const int64_t* order, int mode, double relax,
                  double* phi_trace) {
   int a0 = agent < 0 ? 0 : agent, a1 = agent < 0 ? S->N : agent + 1;
   double pscale = agent < 0 ? 1.0 : 1.0 / S->N;
@@ -367,6 +371,7 @@ int orc_icd_pass(const orc_state* S, int agent, double sigma, const double* v,
         alpha = 0.5 * (lo + hi);
       }
     }
+    alpha *= relax;
     z[s] = zs + alpha;
     for (int a = a0; a < a1; ++a)
       for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t)
@@ -385,7 +390,7 @@ int orc_icd_pass(const orc_state* S, int agent, double sigma, const double* v,
  */
 int orc_mace_solve(const orc_state* S, double rho, double sigma, int sweeps,
                    int max_iters, double tol, double* w_io, const int64_t* order,
-                   int mode, double* x_out, double* X_out, double* resid) {
+                   int mode, double relax, double* x_out, double* X_out, double* resid) {
   int N = S->N;
   int64_t n = S->n;
   double* w = (double*)malloc(sizeof(double) * N * n);
@@ -419,7 +424,7 @@ int orc_mace_solve(const orc_state* S, double rho, double sigma, int sweeps,
 #pragma omp parallel for schedule(static, 1)
     for (int a = 0; a < N; ++a)
       for (int sw = 0; sw < sweeps; ++sw)
-        orc_icd_pass(S, a, sigma, v + a * n, X + a * n, e, order, mode, NULL);
+        orc_icd_pass(S, a, sigma, v + a * n, X + a * n, e, order, mode, relax, NULL);
     /* stopping statistic, summed in agent order */
     double num = 0.0, den = 0.0, dx = 0.0;
     for (int a = 0; a < N; ++a)
@@ -465,7 +470,7 @@ int orc_prox(const orc_state* S, int agent, double sigma, const double* v,
   int it = 0;
   for (; it < max_passes; ++it) {
     memcpy(zo, z, sizeof(double) * S->n);
-    orc_icd_pass(S, agent, sigma, v, z, e, NULL, mode, NULL);
+    orc_icd_pass(S, agent, sigma, v, z, e, NULL, mode, 1.0, NULL);
     double dm = 0.0, zm = 0.0;
     for (int64_t s = 0; s < S->n; ++s) {
       double d = fabs(z[s] - zo[s]);
@@ -492,7 +497,7 @@ int orc_centralized_icd(const orc_state* S, double* x, int max_passes, double rt
   int it = 0;
   for (; it < max_passes; ++it) {
     memcpy(xo, x, sizeof(double) * S->n);
-    orc_icd_pass(S, -1, 0.0, NULL, x, e, NULL, mode, NULL);
+    orc_icd_pass(S, -1, 0.0, NULL, x, e, NULL, mode, 1.0, NULL);
     double dm = 0.0, zm = 0.0;
     for (int64_t s = 0; s < S->n; ++s) {
       double d = fabs(x[s] - xo[s]);

@@ -1,0 +1,234 @@
+"""Python binding of the MI355X MACE library (libmace.so, C ABI in include/mace.h).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of the library.  torch is used, when a caller wants it, only to hold
+device memory and streams (``solve_dev`` takes ``tensor.data_ptr()`` values).
+The library must have been built (``paper_1911_09278_amd.build.build()``);
+importing this package raises if it has not.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libmace.so")
+
+MACE_OK = 0
+MACE_E_ARG = -1
+MACE_E_MATRIX = -2
+MACE_E_PARTITION = -3
+MACE_E_NOMEM = -4
+MACE_E_HIP = -5
+MACE_E_NONFINITE = -6
+MACE_W_MAXITER = 1
+
+
+class MaceError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mace error {code}: {msg}")
+        self.code = code
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("n_views", ctypes.c_int32), ("n_channels", ctypes.c_int32)]
+
+
+class Prior(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("sigma_x", ctypes.c_double), ("p", ctypes.c_double),
+                ("q", ctypes.c_double), ("T", ctypes.c_double), ("b_edge", ctypes.c_double),
+                ("b_diag", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("sv_size", ctypes.c_int32),
+                ("rows_per_agent", ctypes.c_int32), ("fp32_tail_iters", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("equits", ctypes.c_double), ("status", ctypes.c_int32),
+                ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
+                ("iter_ms", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1911_09278_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.mace_load_system.argtypes = [P(Geom), vp, vp, vp, i32, vp, P(Opts), P(vp)]
+    L.mace_load_system.restype = ctypes.c_int
+    L.mace_solve.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, P(Info)]
+    L.mace_solve.restype = ctypes.c_int
+    L.mace_solve_dev.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, P(Info), vp]
+    L.mace_solve_dev.restype = ctypes.c_int
+    L.mace_prox.argtypes = [vp, i32, vp, vp, P(Prior), d, vp, vp, i32, vp]
+    L.mace_prox.restype = ctypes.c_int
+    L.mace_visit_order.argtypes = [vp, vp]
+    L.mace_visit_order.restype = ctypes.c_int
+    L.mace_get_state.argtypes = [vp, vp, vp]
+    L.mace_get_state.restype = ctypes.c_int
+    L.mace_get_error_sinogram.argtypes = [vp, vp]
+    L.mace_get_error_sinogram.restype = ctypes.c_int
+    L.mace_set_relaxation.argtypes = [vp, d]
+    L.mace_set_relaxation.restype = ctypes.c_int
+    L.mace_set_timing.argtypes = [vp, i32]
+    L.mace_set_timing.restype = ctypes.c_int
+    L.mace_system_bytes.argtypes = [vp]
+    L.mace_system_bytes.restype = i64
+    L.mace_check_layout.argtypes = [P(Geom), vp, vp, vp, i32, vp, P(Opts), vp]
+    L.mace_check_layout.restype = ctypes.c_int
+    L.mace_free_system.argtypes = [vp]
+    L.mace_free_system.restype = None
+    L.mace_last_error.argtypes = []
+    L.mace_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_lib = _load()
+
+# Entry points of the C ABI, by name.
+EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_dev", "mace_prox", "mace_visit_order",
+            "mace_get_state", "mace_get_error_sinogram", "mace_system_bytes", "mace_check_layout", "mace_set_timing",
+            "mace_set_relaxation",
+            "mace_free_system", "mace_last_error")
+
+
+def last_error() -> str:
+    return _lib.mace_last_error().decode()
+
+
+def _check(rc, allow=(MACE_OK, MACE_W_MAXITER)):
+    if rc not in allow:
+        raise MaceError(rc, last_error())
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def make_prior(kind=0, sigma_x=0.02, p=2.0, q=2.0, T=1.0, b_edge=0.0, b_diag=0.0) -> Prior:
+    return Prior(int(kind), float(sigma_x), float(p), float(q), float(T), float(b_edge),
+                 float(b_diag))
+
+
+def check_layout(nx, ny, n_views, n_channels, col_ptr, row, val, n_agents, view_to_agent=None,
+                 precision=0, sv_size=0, rows_per_agent=0, fp32_tail_iters=0) -> int:
+    """Host-only dry run of the device layout and schedules (no GPU needed).
+    Returns the LDS bytes per workgroup; raises MaceError on any bad index."""
+    cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+    rw = np.ascontiguousarray(row, dtype=np.int32)
+    vl = np.ascontiguousarray(val, dtype=np.float32)
+    va = None if view_to_agent is None else np.ascontiguousarray(view_to_agent, dtype=np.int32)
+    g = Geom(int(nx), int(ny), int(n_views), int(n_channels))
+    o = Opts(int(precision), int(sv_size), int(rows_per_agent), int(fp32_tail_iters), 0)
+    lds = ctypes.c_int64(0)
+    _check(_lib.mace_check_layout(ctypes.byref(g), _ptr(cp), _ptr(rw), _ptr(vl), int(n_agents),
+                                  _ptr(va), ctypes.byref(o), ctypes.byref(lds)))
+    return int(lds.value)
+
+
+class System:
+    """A loaded scanner geometry: repacked system matrix and view partition."""
+
+    def __init__(self, nx, ny, n_views, n_channels, col_ptr, row, val, n_agents,
+                 view_to_agent=None, precision=0, sv_size=0, rows_per_agent=0,
+                 fp32_tail_iters=0, hbm_budget_bytes=0):
+        self._h = None
+        cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+        rw = np.ascontiguousarray(row, dtype=np.int32)
+        vl = np.ascontiguousarray(val, dtype=np.float32)
+        va = None if view_to_agent is None else np.ascontiguousarray(view_to_agent, dtype=np.int32)
+        self.geom = Geom(int(nx), int(ny), int(n_views), int(n_channels))
+        self.nx, self.ny = int(nx), int(ny)
+        self.n = self.nx * self.ny
+        self.n_rows = int(n_views) * int(n_channels)
+        self.N = int(n_agents)
+        opts = Opts(int(precision), int(sv_size), int(rows_per_agent), int(fp32_tail_iters),
+                    int(hbm_budget_bytes))
+        h = ctypes.c_void_p()
+        _check(_lib.mace_load_system(ctypes.byref(self.geom), _ptr(cp), _ptr(rw), _ptr(vl),
+                                     self.N, _ptr(va), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            _lib.mace_free_system(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def matrix_bytes(self) -> int:
+        return int(_lib.mace_system_bytes(self._h))
+
+    def solve(self, y, lam, prior: Prior, rho, sigma, max_iters, tol=0.0, sweeps=1,
+              w_init=None):
+        """Host arrays in, (x, info) out."""
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        ll = np.ascontiguousarray(lam, dtype=np.float32)
+        if yy.size != self.n_rows or ll.size != self.n_rows:
+            raise ValueError("y / lambda have the wrong size")
+        wi = None if w_init is None else np.ascontiguousarray(w_init, dtype=np.float32)
+        if wi is not None and wi.size != self.N * self.n:
+            raise ValueError("w_init has the wrong size")
+        x = np.empty(self.n, dtype=np.float32)
+        info = Info()
+        rc = _lib.mace_solve(self._h, _ptr(yy), _ptr(ll), ctypes.byref(prior), float(rho),
+                             float(sigma), int(sweeps), int(max_iters), float(tol), _ptr(wi),
+                             _ptr(x), ctypes.byref(info))
+        _check(rc)
+        return x, info
+
+    def solve_dev(self, y_ptr, lam_ptr, prior: Prior, rho, sigma, max_iters, x_ptr, tol=0.0,
+                  sweeps=1, w_init_ptr=None, stream_ptr=None):
+        """Device pointers (e.g. torch tensor.data_ptr()) in; returns info."""
+        info = Info()
+        rc = _lib.mace_solve_dev(self._h, ctypes.c_void_p(y_ptr), ctypes.c_void_p(lam_ptr),
+                                 ctypes.byref(prior), float(rho), float(sigma), int(sweeps),
+                                 int(max_iters), float(tol),
+                                 None if w_init_ptr is None else ctypes.c_void_p(w_init_ptr),
+                                 ctypes.c_void_p(x_ptr), ctypes.byref(info),
+                                 None if stream_ptr is None else ctypes.c_void_p(stream_ptr))
+        _check(rc)
+        return info
+
+    def prox(self, agent, y, lam, prior: Prior, sigma, v, x_init, sweeps=1):
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        ll = np.ascontiguousarray(lam, dtype=np.float32)
+        vv = np.ascontiguousarray(v, dtype=np.float32)
+        xi = np.ascontiguousarray(x_init, dtype=np.float32)
+        out = np.empty(self.n, dtype=np.float32)
+        _check(_lib.mace_prox(self._h, int(agent), _ptr(yy), _ptr(ll), ctypes.byref(prior),
+                              float(sigma), _ptr(vv), _ptr(xi), int(sweeps), _ptr(out)))
+        return out
+
+    def visit_order(self):
+        o = np.empty(self.n, dtype=np.int64)
+        _check(_lib.mace_visit_order(self._h, _ptr(o)))
+        return o
+
+    def set_relaxation(self, gamma):
+        _check(_lib.mace_set_relaxation(self._h, float(gamma)))
+
+    def set_timing(self, enable=True):
+        _check(_lib.mace_set_timing(self._h, 1 if enable else 0))
+
+    def error_sinogram(self):
+        e = np.empty(self.n_rows, dtype=np.float32)
+        _check(_lib.mace_get_error_sinogram(self._h, _ptr(e)))
+        return e
+
+    def state(self):
+        w = np.empty(self.N * self.n, dtype=np.float32)
+        X = np.empty(self.N * self.n, dtype=np.float32)
+        _check(_lib.mace_get_state(self._h, _ptr(w), _ptr(X)))
+        return w.reshape(self.N, self.n), X.reshape(self.N, self.n)

@@ -1,0 +1,74 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mace {
+
+// One row of 16 lanes works on one super-voxel; a 256-thread workgroup holds
+// 4 waves x 4 rows.
+constexpr int kRowLanes = 16;
+constexpr int kRowsPerBlock = 16;
+constexpr int kBlockThreads = 256;
+constexpr int kMaxSlots = 8;  // views per agent <= 16 * kMaxSlots
+
+// Band of one (agent, super-voxel, agent-local view): channels
+// [cmin, cmin + width) of that view, staged in LDS from row lds_row on.
+struct BandEnt {
+  uint32_t gstart;   // index of (view, cmin) in the agent's sinogram block
+  uint16_t lds_row;  // first LDS row of the band
+  uint16_t width;    // channels in the band (0: the view misses the SV)
+};
+
+enum KernelMode { kSweep = 0, kTheta2 = 1, kRefresh = 2 };
+
+struct SvArgs {
+  int nx, ny, n;        // image
+  int S, gx, n_sv;      // super-voxel side, grid width, count
+  int kpad;             // record entries per pixel (slots * 16)
+  int bmax;             // LDS rows reserved per super-voxel (even)
+  int wmax;             // widest band of one view (channels)
+  const int* tasks;     // [R][T] task = agent * n_sv + sv, or -1
+  int T, R;
+  const int* sv_pix0;   // [n_sv + 1] first record of each super-voxel
+  const float2* aval;   // FP32 records: (a0, a1) per (agent, pixel, view slot)
+  const __half2* hval;  // FP16 records (precision 1), scaled by hscale
+  const float* hscale;  // [N * n] per (agent, pixel) scale of the FP16 values
+  const uint16_t* aoff; // LDS row of channel d0 per (agent, pixel, view slot)
+  const BandEnt* band;  // [(agent * n_sv + sv) * kpad + view]
+  const int* band_rows; // [agent * n_sv + sv] rows B of the band (dummy rows at B, B+1)
+  int64_t estride;      // per-agent stride of e / lam blocks
+  float* e;             // error sinogram y - A X, agent blocks
+  const float* lam;     // inverse-variance weights, agent blocks
+  float* X;             // [N][n] agent states
+  float* w;             // [N][n] Mann state
+  const float* wbar;    // [n] mean of w at the start of the iteration
+  float* th2;           // [N][n] theta2 = sum_r A_rs^2 Lambda_r
+  double* part;         // [R][4] residual partials of this launch
+  int kind;             // 0 quadratic, 1 q-GGMRF (p = 2)
+  float invN, is2, rho;
+  float relax;          // scale of each coordinate step (1 = exact minimiser)
+  float bedge, bdiag;
+  float c0;             // 1 / sigma_x^2
+  float inv_tsx;        // 1 / (T sigma_x)
+  float qexp;           // p - q = 2 - q
+  float qhalf;          // q / p = q / 2
+  int mann;             // apply the reflection + Mann update at the end
+  int fp16;             // read the FP16 records
+  int strict;           // one SV of an agent at a time: stage e after the previous flush
+};
+
+// Launchers (defined in mace_kernels.hip).
+hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
+size_t sv_lds_bytes(int bmax, int S);
+hipError_t launch_epilogue(const float* w, float* wbar, int N, int n, const double* part,
+                           int nparts, double* resid, int* counter, int max_iters,
+                           hipStream_t st);
+hipError_t launch_gather_rows(float* dst, const float* src, const int* row_src, int64_t count,
+                              hipStream_t st);
+hipError_t launch_fill(float* dst, float v, int64_t count, hipStream_t st);
+hipError_t launch_broadcast_mean(const float* w, float* wbar, float* X, int N, int n,
+                                 hipStream_t st);
+hipError_t launch_copy(float* dst, const float* src, int64_t count, hipStream_t st);
+
+}  // namespace mace

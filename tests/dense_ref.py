@@ -96,3 +96,16 @@ def pu_mace_linear_map(Hs, bs, sigma, rho):
     M[:Nn, Nn:] = 2 * rho * P
     c = np.concatenate([2 * rho * c0, c0])
     return M, c
+
+
+def sor_pass_closed_form(H, b, x, v, sigma, omega):
+    """Successive over-relaxation sweep (textbook SOR) for
+    (H + I/sigma^2) z = b + v/sigma^2 from z = x:
+      (D + omega L) z = omega (b + v/sigma^2) - (omega L^T + (omega - 1) D) x
+    with D the diagonal of H + I/sigma^2 and L the strict lower triangle of H."""
+    n = H.shape[0]
+    M = H + np.eye(n) / sigma ** 2
+    L = np.tril(M, -1)
+    D = np.diag(np.diag(M))
+    rhs = omega * (b + v / sigma ** 2) - (omega * L.T + (omega - 1.0) * D) @ x
+    return np.linalg.solve(D + omega * L, rhs)

@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI that run without a GPU: the library loads,
+exports every function include/mace.h declares, and rejects malformed input
+before touching the device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import mace_inputs as mi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mace.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mace_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1911_09278_amd as m
+    names = _declared()
+    assert "mace_load_system" in names and "mace_solve" in names and "mace_prox" in names
+    for nm in names:
+        assert hasattr(m._lib, nm), nm
+    assert set(names) <= set(m.EXPORTED)
+
+
+def test_library_has_no_oracle_dependency():
+    # the product library links no oracle code
+    import paper_1911_09278_amd as m
+    out = open(m.LIB_PATH, "rb").read()
+    assert b"orc_" not in out and b"mace_oracle" not in out
+
+
+def _small():
+    g = mi.Geometry(16, 16, 24, 24)
+    return g, mi.system_matrix(g)
+
+
+def test_rejects_malformed_csc():
+    import paper_1911_09278_amd as m
+    g, (cp, row, val) = _small()
+    bad = row.copy()
+    bad[5] = bad[4]
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, bad, val, 4)
+    assert e.value.code == m.MACE_E_MATRIX
+    bad = row.copy()
+    bad[0] = g.n_rows
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, bad, val, 4)
+    assert e.value.code == m.MACE_E_MATRIX
+    v2 = val.copy()
+    v2[3] = np.nan
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, v2, 4)
+    assert e.value.code == m.MACE_E_MATRIX
+    cp2 = cp.copy()
+    cp2[0] = 1
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp2, row, val, 4)
+    assert e.value.code == m.MACE_E_MATRIX
+
+
+def test_rejects_bad_partition_and_args():
+    import paper_1911_09278_amd as m
+    g, (cp, row, val) = _small()
+    va = np.zeros(g.n_views, dtype=np.int32)  # agents 1..3 own nothing
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 4, view_to_agent=va)
+    assert e.value.code == m.MACE_E_PARTITION
+    va = np.full(g.n_views, 7, dtype=np.int32)
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 4, view_to_agent=va)
+    assert e.value.code == m.MACE_E_PARTITION
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 0)
+    assert e.value.code == m.MACE_E_ARG
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 4, precision=3)
+    assert e.value.code == m.MACE_E_ARG
+    # one agent with more than 128 views
+    g2 = mi.Geometry(8, 8, 130, 12)
+    cp3, row3, val3 = mi.system_matrix(g2)
+    with pytest.raises(m.MaceError) as e:
+        m.System(g2.nx, g2.ny, g2.n_views, g2.n_channels, cp3, row3, val3, 1)
+    assert e.value.code == m.MACE_E_PARTITION
+
+
+def test_rejects_three_channel_footprint():
+    # channel spacing 0.4 mm: a 1 mm pixel covers up to 4 channels per view
+    import paper_1911_09278_amd as m
+    g = mi.Geometry(8, 8, 6, 40, pix=1.0, chan=0.4)
+    cp, row, val = mi.system_matrix(g)
+    with pytest.raises(m.MaceError) as e:
+        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2)
+    assert e.value.code == m.MACE_E_MATRIX
+
+
+LAYOUT_CASES = [
+    (mi.Geometry(32, 32, 64, 48), 4, 4), (mi.Geometry(42, 38, 180, 64), 4, 4),
+    (mi.Geometry(24, 24, 100, 40), 2, 8), (mi.Geometry(20, 20, 30, 32), 1, 4),
+    (mi.Geometry(32, 32, 90, 48), 3, 4), (mi.Geometry(40, 40, 96, 60), 4, 4),
+    (mi.Geometry(48, 48, 96, 72), 4, 4), (mi.Geometry(64, 64, 90, 96), 4, 4),
+    (mi.Geometry(33, 17, 45, 40), 3, 8), (mi.Geometry(16, 16, 24, 24), 8, 4),
+]
+
+
+@pytest.mark.parametrize("case", LAYOUT_CASES, ids=lambda c: f"{c[0].nx}x{c[0].ny}_N{c[1]}_S{c[2]}")
+def test_device_layout_indices_in_bounds(case):
+    import paper_1911_09278_amd as m
+    g, N, S = case
+    cp, row, val = mi.system_matrix(g)
+    for prec in (0, 1):
+        lds = m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=S,
+                             precision=prec, fp32_tail_iters=2)
+        assert 0 < lds <= 160 * 1024
+
+
+@pytest.mark.slow
+def test_device_layout_scan512():
+    import paper_1911_09278_amd as m
+    w = mi.WORKLOADS["scan512"]
+    g = w.geom
+    cp, row, val = mi.system_matrix(g)
+    lds = m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents)
+    assert lds <= 160 * 1024

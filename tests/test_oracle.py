@@ -51,6 +51,32 @@ def test_P1_icd_pass_equals_gauss_seidel_closed_form(N, agent):
     np.testing.assert_allclose(e[r], y[r] - A[r] @ z, atol=1e-10)
 
 
+@pytest.mark.parametrize("omega", [0.5, 0.8])
+def test_P1_relaxed_pass_equals_sor_closed_form(omega):
+    # relax scales every coordinate step: a quadratic pass is then textbook SOR
+    g = mi.Geometry(8, 8, 12, 12)
+    sx, sigma = 0.01, 0.02
+    O, A, lam, y, va = _problem(g, 24, 2, 0, sx)
+    Hs, bs = dr.agent_system(g, A, lam, y, dr.laplacian(8, 8), sx, va, 2)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0, 0.05, g.n)
+    v = rng.uniform(0, 0.05, g.n)
+    z = x.copy()
+    e = O.error_sinogram(x, agent=1)
+    O.icd_pass(1, sigma, v, z, e, relax=omega)
+    ref = dr.sor_pass_closed_form(Hs[1], bs[1], x, v, sigma, omega)
+    np.testing.assert_allclose(z, ref, rtol=1e-11, atol=1e-14)
+
+
+def test_relaxation_keeps_the_fixed_point(quad32):
+    # under-relaxed passes reach the same MAP fixed point (the stationarity
+    # argument of Lemma B.1 does not depend on the step length)
+    d = quad32
+    r = d["O"].mace_solve(d["rho"], d["sigma"], 8000, tol=1e-13, relax=0.6)
+    assert r["resid"][-1] < 1e-13
+    assert np.linalg.norm(r["x"] - d["xmap"]) / np.linalg.norm(d["xmap"]) < 1e-9
+
+
 def test_P1_visiting_order_is_respected():
     g = mi.Geometry(8, 8, 12, 12)
     O, A, lam, y, va = _problem(g, 22, 2, 0, 0.01)
