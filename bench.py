@@ -51,7 +51,7 @@ def cpu_baseline(g, cp, row, val, scan, va, w8, sigma, budget_s=20.0):
     t0 = time.perf_counter()
     O.mace_solve(w8.rho, sigma, 1)
     t1 = time.perf_counter() - t0
-    iters = max(1, min(10, int(budget_s / max(t1, 1e-3))))
+    iters = max(1, min(200, int(budget_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
     O.mace_solve(w8.rho, sigma, iters)
     dt = time.perf_counter() - t0
@@ -71,7 +71,10 @@ def main():
     ap.add_argument("--sigma", type=float, default=2e-4)
     ap.add_argument("--rows-per-agent", type=int, default=0)
     ap.add_argument("--sv-size", type=int, default=0)
+    ap.add_argument("--relax", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -79,6 +82,18 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        n = 1 << 28  # 2^28 floats = 1 GiB
+        a = torch.empty(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "launches": 3}))
+        return
     import mace_inputs as mi
     from paper_1911_09278_amd import build as libbuild
     if not os.path.exists(libbuild.LIB):
@@ -96,6 +111,7 @@ def main():
     log(f"nnz={nnz}; loading system")
     sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w8.n_agents,
                     rows_per_agent=args.rows_per_agent, sv_size=args.sv_size)
+    sysm.set_relaxation(args.relax)
     prior = m.make_prior(w8.prior_kind, w8.sigma_x, w8.p, w8.q, w8.T)
     dev = torch.device("cuda:0")
     y = torch.from_numpy(scan.y).to(dev)
@@ -152,8 +168,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "scan512: 512x512 image, 720 views, 736 channels, 16 agents, "
                                "q-GGMRF p=2 q=1.2 T=1 sigma_x=0.01, rho=0.8",
-                   "mann_iters": args.iters, "sigma": args.sigma, "nnz": nnz,
-                   "sv_size": args.sv_size or 4},
+                   "mann_iters": args.iters, "sigma": args.sigma, "relaxation": args.relax,
+                   "nnz": nnz, "sv_size": args.sv_size or 8,
+                   "rows_per_agent": args.rows_per_agent or "auto"},
         "hbm_gbps_algorithmic": bytes_iter * args.steps * args.iters / dt / 1e9,
         "latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
         "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),

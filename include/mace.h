@@ -75,12 +75,16 @@ typedef struct {
 typedef struct {
   int32_t precision;      /* 0: A values FP32 (default); 1: FP16 with a per
                              (agent, pixel) FP32 scale */
-  int32_t sv_size;        /* super-voxel side S in pixels; 0 = default (4) */
-  int32_t rows_per_agent; /* concurrent super-voxels per agent; 0 = automatic;
-                             1 = sequential (one super-voxel of an agent at a
+  int32_t sv_size;        /* super-voxel side S in pixels: 4 or 8; 0 = 8 for
+                             images of at least 256 x 256 pixels, else 4 */
+  int32_t rows_per_agent; /* concurrent super-voxels per agent; 0 = automatic
+                             (about 4096 in total over the agents); 1 =
+                             sequential (one super-voxel of an agent at a
                              time: the visiting order of mace_visit_order) */
   int32_t fp32_tail_iters;/* with precision 1: last iterations in FP32 A */
   int64_t hbm_budget_bytes; /* 0 = no limit */
+  int32_t refresh_every;  /* recompute e = y - A X_i every this many Mann
+                             iterations to stop FP32 drift (0 = never) */
 } mace_opts;
 
 typedef struct {
@@ -157,8 +161,9 @@ int mace_get_state(const mace_system* sys, float* w, float* X);
 int mace_get_error_sinogram(const mace_system* sys, float* e);
 
 /*
- * Scale of every ICD coordinate step, gamma in (0, 1] (default 1): z_s +=
- * gamma * alpha_s.  gamma = 1 is Algorithm 2's exact coordinate minimisation
+ * Scale of every ICD coordinate step, gamma in (0, 1]: z_s += gamma * alpha_s.
+ * Default: 1 for the sequential schedule, 0.5 when super-voxels of an agent
+ * run concurrently.  gamma = 1 is Algorithm 2's exact coordinate minimisation
  * (of the prior's quadratic majoriser); gamma < 1 under-relaxes the partial
  * update.  A pixel is left unchanged exactly when its coordinate derivative
  * vanishes for any gamma, so the fixed points -- and, by Theorem 1, the MAP

@@ -46,7 +46,7 @@ class Prior(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sv_size", ctypes.c_int32),
                 ("rows_per_agent", ctypes.c_int32), ("fp32_tail_iters", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64)]
+                ("hbm_budget_bytes", ctypes.c_int64), ("refresh_every", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -128,7 +128,7 @@ def check_layout(nx, ny, n_views, n_channels, col_ptr, row, val, n_agents, view_
     vl = np.ascontiguousarray(val, dtype=np.float32)
     va = None if view_to_agent is None else np.ascontiguousarray(view_to_agent, dtype=np.int32)
     g = Geom(int(nx), int(ny), int(n_views), int(n_channels))
-    o = Opts(int(precision), int(sv_size), int(rows_per_agent), int(fp32_tail_iters), 0)
+    o = Opts(int(precision), int(sv_size), int(rows_per_agent), int(fp32_tail_iters), 0, 0)
     lds = ctypes.c_int64(0)
     _check(_lib.mace_check_layout(ctypes.byref(g), _ptr(cp), _ptr(rw), _ptr(vl), int(n_agents),
                                   _ptr(va), ctypes.byref(o), ctypes.byref(lds)))
@@ -140,7 +140,7 @@ class System:
 
     def __init__(self, nx, ny, n_views, n_channels, col_ptr, row, val, n_agents,
                  view_to_agent=None, precision=0, sv_size=0, rows_per_agent=0,
-                 fp32_tail_iters=0, hbm_budget_bytes=0):
+                 fp32_tail_iters=0, hbm_budget_bytes=0, refresh_every=0):
         self._h = None
         cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
         rw = np.ascontiguousarray(row, dtype=np.int32)
@@ -152,7 +152,7 @@ class System:
         self.n_rows = int(n_views) * int(n_channels)
         self.N = int(n_agents)
         opts = Opts(int(precision), int(sv_size), int(rows_per_agent), int(fp32_tail_iters),
-                    int(hbm_budget_bytes))
+                    int(hbm_budget_bytes), int(refresh_every))
         h = ctypes.c_void_p()
         _check(_lib.mace_load_system(ctypes.byref(self.geom), _ptr(cp), _ptr(rw), _ptr(vl),
                                      self.N, _ptr(va), ctypes.byref(opts), ctypes.byref(h)))

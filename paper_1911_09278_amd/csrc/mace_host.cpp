@@ -89,6 +89,7 @@ struct mace_system {
   int precision = 0;
   int rows_per_agent = 0;
   int fp32_tail = 0;
+  int refresh_every = 0;
   int64_t estride = 0;
   std::vector<int> view_agent;             // [n_views]
   std::vector<std::vector<int>> views;     // agent -> its views, ascending
@@ -111,7 +112,7 @@ struct mace_system {
   int resid_cap = 0, part_cap = 0;
   int64_t matrix_bytes = 0;
   bool timing = false;
-  double relax = 1.0;
+  double relax = 0.0;  // 0: automatic (1 for the sequential schedule, 0.5 otherwise)
   std::vector<hipEvent_t> ev;  // timing events, created on demand
   ~mace_system() {
     for (auto e : ev) (void)hipEventDestroy(e);
@@ -538,11 +539,12 @@ static Schedule* get_schedule(mace_system* s, int only_agent, int P) {
   return out;
 }
 
+// Concurrent super-voxels per agent: enough 16-lane rows in total (about
+// 4096, i.e. 1024 waves) to keep every CU busy, at most the SVs of one colour.
 static int default_rows_per_agent(const mace_system* s) {
   if (s->rows_per_agent > 0) return s->rows_per_agent;
-  // about one concurrently updated SV of an agent per ray: P * S ~ image width
-  int P = std::max(1, std::max(s->nx, s->ny) / s->S);
   const int per_colour = (s->n_sv + 3) / 4;
+  const int P = (4096 + s->N - 1) / s->N;
   return std::max(1, std::min(P, per_colour));
 }
 
@@ -600,7 +602,7 @@ static void fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, dou
   a.wbar = s->wbar.p;
   a.th2 = s->th2.p;
   a.invN = (float)(1.0 / s->N);
-  a.relax = (float)s->relax;
+  a.relax = (float)(s->relax > 0.0 ? s->relax : (default_rows_per_agent(s) == 1 ? 1.0 : 0.5));
   a.rho = (float)rho;
   a.is2 = sigma > 0 ? (float)(1.0 / (sigma * sigma)) : 0.f;
   if (pr) {
@@ -656,10 +658,13 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
     if (opts->rows_per_agent < 0) return fail(MACE_E_ARG, "rows_per_agent must be >= 0");
     if (opts->fp32_tail_iters < 0) return fail(MACE_E_ARG, "fp32_tail_iters must be >= 0");
     s->precision = opts->precision;
-    if (opts->sv_size > 0) s->S = opts->sv_size;
+    s->S = opts->sv_size;
     s->rows_per_agent = opts->rows_per_agent;
     s->fp32_tail = opts->precision == 1 ? opts->fp32_tail_iters : 0;
+    if (opts->refresh_every < 0) return fail(MACE_E_ARG, "refresh_every must be >= 0");
+    s->refresh_every = opts->refresh_every;
   }
+  if (s->S == 0) s->S = std::min(s->nx, s->ny) >= 256 ? 8 : 4;
   int rc = build_partition(s.get(), view_to_agent);
   if (rc) return rc;
   rc = check_matrix(s.get(), col_ptr, row_idx, val);
@@ -673,9 +678,9 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
     rc = upload_pack(s.get(), hp);
     if (rc) return rc;
   }
-  if (sv_lds_bytes(s->bmax, s->S) > 160 * 1024)
+  if (sv_lds_bytes(s->bmax, s->S, s->kpad) > 160 * 1024)
     return fail(MACE_E_ARG, "super-voxel band needs %zu bytes of LDS per workgroup; use a smaller sv_size",
-                sv_lds_bytes(s->bmax, s->S));
+                sv_lds_bytes(s->bmax, s->S, s->kpad));
   *out = s.release();
   g_err.clear();
   return MACE_OK;
@@ -701,10 +706,11 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
     if (opts->sv_size != 0 && opts->sv_size != 4 && opts->sv_size != 8)
       return fail(MACE_E_ARG, "sv_size must be 0 (default 4), 4 or 8");
     s.precision = opts->precision;
-    if (opts->sv_size > 0) s.S = opts->sv_size;
+    s.S = opts->sv_size;
     s.rows_per_agent = opts->rows_per_agent;
     s.fp32_tail = opts->precision == 1 ? opts->fp32_tail_iters : 0;
   }
+  if (s.S == 0) s.S = std::min(s.nx, s.ny) >= 256 ? 8 : 4;
   int rc = build_partition(&s, view_to_agent);
   if (rc) return rc;
   rc = check_matrix(&s, col_ptr, row_idx, val);
@@ -724,8 +730,8 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
     }
     if (only >= 2) break;
   }
-  if (lds_bytes) *lds_bytes = (int64_t)sv_lds_bytes(s.bmax, s.S);
-  if (sv_lds_bytes(s.bmax, s.S) > 160 * 1024) return fail(MACE_E_ARG, "LDS per workgroup exceeds 160 KiB");
+  if (lds_bytes) *lds_bytes = (int64_t)sv_lds_bytes(s.bmax, s.S, s.kpad);
+  if (sv_lds_bytes(s.bmax, s.S, s.kpad) > 160 * 1024) return fail(MACE_E_ARG, "LDS per workgroup exceeds 160 KiB");
   return MACE_OK;
 }
 
@@ -801,7 +807,7 @@ static int start_scan(mace_system* s, const float* y, const float* lam, const fl
   fill_args(s, a, pr, 0.8, sigma, fp16);
   a.R = sch->R;
   a.strict = P == 1 ? 1 : 0;
-  const size_t lds = sv_lds_bytes(s->bmax, s->S);
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
   for (int c = 0; c < 4; ++c) {
     a.tasks = sch->tasks[c].p;
     a.T = sch->T[c];
@@ -829,7 +835,7 @@ static int solve_impl(mace_system* s, const float* y, const float* lam, const ma
   rc = start_scan(s, y, lam, w_init, pr, sigma, fp16, st);
   if (rc) return rc;
   HIP_OK(hipMemsetAsync(s->counter.p, 0, sizeof(int), st));
-  const size_t lds = sv_lds_bytes(s->bmax, s->S);
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
   SvArgs a;
   fill_args(s, a, pr, rho, sigma, fp16);
   a.R = sch->R;
@@ -859,6 +865,16 @@ static int solve_impl(mace_system* s, const float* y, const float* lam, const ma
         a.tasks = sch->tasks[c].p;
         a.T = sch->T[c];
         HIP_OK(launch_sv(a, kTheta2, s->slots, sch->grid, lds, st));
+        HIP_OK(launch_sv(a, kRefresh, s->slots, sch->grid, lds, st));
+      }
+    }
+    if (s->refresh_every > 0 && it > 0 && it % s->refresh_every == 0 && !refreshed) {
+      // rebuild e = y - A X_i from the agent states (FP32 drift of the
+      // incrementally updated error sinogram)
+      HIP_OK(launch_copy(s->e.p, s->yb.p, (int64_t)s->N * s->estride, st));
+      for (int c = 0; c < 4; ++c) {
+        a.tasks = sch->tasks[c].p;
+        a.T = sch->T[c];
         HIP_OK(launch_sv(a, kRefresh, s->slots, sch->grid, lds, st));
       }
     }
@@ -983,7 +999,7 @@ extern "C" int mace_prox(mace_system* s, int32_t agent, const float* y, const fl
   HIP_OK(hipMemcpy(s->wbar.p, dv.p, sizeof(float) * s->n, hipMemcpyDeviceToDevice));
   HIP_OK(hipMemcpy(s->w.p + (size_t)agent * s->n, dv.p, sizeof(float) * s->n, hipMemcpyDeviceToDevice));
   const bool fp16 = s->precision == 1;
-  const size_t lds = sv_lds_bytes(s->bmax, s->S);
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
   SvArgs a;
   fill_args(s, a, pr, 0.5, sigma, fp16);
   a.R = sch->R;

@@ -60,7 +60,7 @@ struct SvArgs {
 
 // Launchers (defined in mace_kernels.hip).
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
-size_t sv_lds_bytes(int bmax, int S);
+size_t sv_lds_bytes(int bmax, int S, int kpad);
 hipError_t launch_epilogue(const float* w, float* wbar, int N, int n, const double* part,
                            int nparts, double* resid, int* counter, int max_iters,
                            hipStream_t st);

@@ -64,12 +64,14 @@ __device__ __forceinline__ float prior_curv(const SvArgs& a, float d) {
   return a.c0 * (1.0f + a.qhalf * s) * __builtin_amdgcn_rcpf(den * den);
 }
 
+template <bool F16>
 __device__ __forceinline__ float2 load_vals(const SvArgs& a, size_t idx, float scale) {
-  if (a.fp16) {
-    float2 f = __half22float2(a.hval[idx]);
+  if constexpr (F16) {
+    const float2 f = __half22float2(a.hval[idx]);
     return make_float2(f.x * scale, f.y * scale);
+  } else {
+    return a.aval[idx];
   }
-  return a.aval[idx];
 }
 
 // Record of one pixel for the lane's view slots: (a0, a1) on channels d0,
@@ -82,22 +84,23 @@ struct Rec {
   int off[SL];
 };
 
-template <int SL>
+template <int SL, bool F16>
 __device__ __forceinline__ void load_rec(const SvArgs& a, size_t rec, int lr, Rec<SL>& r) {
-  const float scale = a.fp16 ? a.hscale[rec] : 1.0f;
+  float scale = 1.0f;
+  if constexpr (F16) scale = a.hscale[rec];
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
     const size_t idx = rec * a.kpad + s * kRowLanes + lr;
-    r.val[s] = load_vals(a, idx, scale);
+    r.val[s] = load_vals<F16>(a, idx, scale);
     r.off[s] = a.aoff[idx];
   }
 }
 
 // LDS bytes of one row: band (e, Lambda) and the staged copy of e over bmax
 // rows, the halo tile (value, inside-image flag), v and theta2 of the SV.
-__host__ __device__ inline size_t row_lds_bytes(int bmax, int S) {
+__host__ __device__ inline size_t row_lds_bytes(int bmax, int S, int kpad) {
   const size_t HS = S + 2;
-  const size_t per_row = (size_t)bmax * 12 + HS * HS * 8 + (size_t)S * S * 8;
+  const size_t per_row = (size_t)bmax * 12 + HS * HS * 8 + (size_t)S * S * 8 + (size_t)kpad * 8;
   const size_t red = kRowLanes * 3 * sizeof(double);  // end-of-kernel reduction
   return per_row > red ? per_row : red;
 }
@@ -121,7 +124,7 @@ struct Stage {
   float t2[PPL];
 };
 
-template <int SL, int MODE, int S>
+template <int SL, int MODE, int S, bool F16>
 __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
   constexpr int WM = (S <= 4) ? 8 : 16;
   constexpr int HS = S + 2;
@@ -131,13 +134,14 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
   const int lr = lane64 & 15;
   const int rib = ((threadIdx.x >> 6) << 2) | (lane64 >> 4);  // row in block
   const int row = blockIdx.x * kRowsPerBlock + rib;
-  const size_t per_row = row_lds_bytes(a.bmax, S);
+  const size_t per_row = row_lds_bytes(a.bmax, S, a.kpad);
   char* base = smem + rib * per_row;
   float2* band = reinterpret_cast<float2*>(base);
   float* e0 = reinterpret_cast<float*>(base + (size_t)a.bmax * 8);
   float2* halo = reinterpret_cast<float2*>(base + (size_t)a.bmax * 12);
   float* vv = reinterpret_cast<float*>(base + (size_t)a.bmax * 12 + (size_t)HS * HS * 8);
   float* t2 = vv + S * S;
+  BandEnt* bents = reinterpret_cast<BandEnt*>(t2 + S * S);  // [kpad]
 
   // neighbour of lanes 0-7: (di, dj) in raster order of the 3x3 block
   const int ndi = (lr < 3) ? -1 : (lr < 5 ? 0 : 1);
@@ -286,98 +290,97 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
       const int pix0 = st.pix0;
       __builtin_amdgcn_wave_barrier();
 
-      // ---- 2. pixel loop (records prefetched kPrefetch pixels ahead; the
-      //         next task is staged after the first pixel) ----
+      // ---- 2. pixel loop: records prefetched kPrefetch pixels ahead; the
+      //         next task is staged right after the first pixel ----
       const size_t rec0 = (size_t)agent * a.n + pix0;
-      Rec<SL> buf[kPrefetch];
+      auto update = [&](const Rec<SL>& cur, int j, int pi, int pj) {
+        const int cidx = (pi + 1) * HS + pj + 1;
+        if (MODE == kSweep) {
+          float part = 0.0f;
+          float2 p0[SL], p1[SL];
 #pragma unroll
-      for (int q = 0; q < kPrefetch; ++q)
-        if (q < npix) load_rec<SL>(a, rec0 + q, lr, buf[q]);
-      bool staged = false;
-      for (int j0 = 0; j0 < npix; j0 += kPrefetch) {
+          for (int s2 = 0; s2 < SL; ++s2) {
+            p0[s2] = band[cur.off[s2]];
+            p1[s2] = band[cur.off[s2] + 1];
+            part += cur.val[s2].x * p0[s2].y * p0[s2].x + cur.val[s2].y * p1[s2].y * p1[s2].x;
+          }
+          const float zs = halo[cidx].x;
+          float gl = -part, hl = 0.0f;
+          if (lr < 8) {
+            const float2 nb = halo[cidx + noff];
+            const float d = zs - nb.x;
+            const float wgt = nbw * nb.y * prior_curv(a, d) * a.invN;
+            gl += wgt * d;
+            hl = wgt;
+          } else if (lr == 8) {
+            gl += a.is2 * (zs - vv[j]);
+          }
+          const float G = row_sum16(gl);
+          const float H = row_sum16(hl);
+          const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(t2[j] + H + a.is2);
 #pragma unroll
-        for (int q = 0; q < kPrefetch; ++q) {
-          const int j = j0 + q;
-          if (j < npix) {
-            const Rec<SL> cur = buf[q];
-            if (j + kPrefetch < npix) load_rec<SL>(a, rec0 + j + kPrefetch, lr, buf[q]);
-            if (!staged) {
-              stage_load(t + 1, st);
-              staged = true;
-            }
-            const int pi = j / sw, pj = j - (j / sw) * sw;
-            const int cidx = (pi + 1) * HS + pj + 1;
-            if (MODE == kSweep) {
-              float part = 0.0f;
-              float2 p0[SL], p1[SL];
+          for (int s2 = 0; s2 < SL; ++s2) {
+            band[cur.off[s2]].x = p0[s2].x - cur.val[s2].x * alpha;
+            band[cur.off[s2] + 1].x = p1[s2].x - cur.val[s2].y * alpha;
+          }
+          if (lr == 0) halo[cidx].x = zs + alpha;
+        } else if (MODE == kTheta2) {
+          float part = 0.0f;
 #pragma unroll
-              for (int s2 = 0; s2 < SL; ++s2) {
-                p0[s2] = band[cur.off[s2]];
-                p1[s2] = band[cur.off[s2] + 1];
-                part += cur.val[s2].x * p0[s2].y * p0[s2].x + cur.val[s2].y * p1[s2].y * p1[s2].x;
-              }
-              const float zs = halo[cidx].x;
-              float gl = -part, hl = 0.0f;
-              if (lr < 8) {
-                const float2 nb = halo[cidx + noff];
-                const float d = zs - nb.x;
-                const float wgt = nbw * nb.y * prior_curv(a, d) * a.invN;
-                gl += wgt * d;
-                hl = wgt;
-              } else if (lr == 8) {
-                gl += a.is2 * (zs - vv[j]);
-              }
-              const float G = row_sum16(gl);
-              const float H = row_sum16(hl);
-              const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(t2[j] + H + a.is2);
+          for (int s2 = 0; s2 < SL; ++s2) {
+            const float l0 = band[cur.off[s2]].y, l1 = band[cur.off[s2] + 1].y;
+            part += cur.val[s2].x * cur.val[s2].x * l0 + cur.val[s2].y * cur.val[s2].y * l1;
+          }
+          const float th = row_sum16(part);
+          if (lr == 0) {
+            const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
+            a.th2[img + pix] = th;
+          }
+        } else {  // kRefresh: accumulate -A x into the band
+          const float xs = halo[cidx].x;
 #pragma unroll
-              for (int s2 = 0; s2 < SL; ++s2) {
-                band[cur.off[s2]].x = p0[s2].x - cur.val[s2].x * alpha;
-                band[cur.off[s2] + 1].x = p1[s2].x - cur.val[s2].y * alpha;
-              }
-              if (lr == 0) halo[cidx].x = zs + alpha;
-            } else if (MODE == kTheta2) {
-              float part = 0.0f;
-#pragma unroll
-              for (int s2 = 0; s2 < SL; ++s2) {
-                const float l0 = band[cur.off[s2]].y, l1 = band[cur.off[s2] + 1].y;
-                part += cur.val[s2].x * cur.val[s2].x * l0 + cur.val[s2].y * cur.val[s2].y * l1;
-              }
-              const float th = row_sum16(part);
-              if (lr == 0) {
-                const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
-                a.th2[img + pix] = th;
-              }
-            } else {  // kRefresh: accumulate -A x into the band
-              const float xs = halo[cidx].x;
-#pragma unroll
-              for (int s2 = 0; s2 < SL; ++s2) {
-                band[cur.off[s2]].x -= cur.val[s2].x * xs;
-                band[cur.off[s2] + 1].x -= cur.val[s2].y * xs;
-              }
-            }
-            __builtin_amdgcn_wave_barrier();
+          for (int s2 = 0; s2 < SL; ++s2) {
+            band[cur.off[s2]].x -= cur.val[s2].x * xs;
+            band[cur.off[s2] + 1].x -= cur.val[s2].y * xs;
           }
         }
+        __builtin_amdgcn_wave_barrier();
+      };
+      if (npix == S * S) {
+        // full super-voxel: straight-line code, every record in its own
+        // registers, so each wait covers exactly the record it needs
+        Rec<SL> buf[S * S];
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) load_rec<SL, F16>(a, rec0 + q, lr, buf[q]);
+#pragma unroll
+        for (int j = 0; j < S * S; ++j) {
+          if (j + kPrefetch < S * S) load_rec<SL, F16>(a, rec0 + j + kPrefetch, lr, buf[j + kPrefetch]);
+          if (j == 0) stage_load(t + 1, st);
+          update(buf[j], j, j / S, j % S);
+        }
+      } else {
+        // ragged super-voxel at the image border
+        for (int j = 0; j < npix; ++j) {
+          Rec<SL> cur;
+          load_rec<SL, F16>(a, rec0 + j, lr, cur);
+          if (j == 0) stage_load(t + 1, st);
+          update(cur, j, j / sw, j - (j / sw) * sw);
+        }
       }
-      if (!staged) stage_load(t + 1, st);
 
-      // ---- 3. write back ----
+      // ---- 3. write back: the band's change goes to the agent's error
+      //         sinogram with atomics, one view per instruction, the 16 lanes
+      //         on consecutive channels (one or two cache lines each) ----
       if (MODE != kTheta2) {
 #pragma unroll
-        for (int sl = 0; sl < SL; ++sl) {
-          const int wdt = (int)cb[sl].width;
-#pragma unroll
-          for (int c = 0; c < WM; ++c)
-            if (c < wdt) {
-              float d = band[cb[sl].lds_row + c].x;
-              if (MODE == kSweep) d -= e0[cb[sl].lds_row + c];
-              atomicAdd(eag + cb[sl].gstart + c, d);
-            }
-          for (int c = WM; c < wdt; ++c) {
-            float d = band[cb[sl].lds_row + c].x;
-            if (MODE == kSweep) d -= e0[cb[sl].lds_row + c];
-            atomicAdd(eag + cb[sl].gstart + c, d);
+        for (int sl = 0; sl < SL; ++sl) bents[sl * kRowLanes + lr] = cb[sl];
+        __builtin_amdgcn_wave_barrier();
+        for (int kl = 0; kl < a.kpad; ++kl) {
+          const BandEnt b = bents[kl];
+          for (int c = lr; c < (int)b.width; c += kRowLanes) {
+            float d = band[b.lds_row + c].x;
+            if (MODE == kSweep) d -= e0[b.lds_row + c];
+            atomicAdd(eag + b.gstart + c, d);
           }
         }
       }
@@ -434,22 +437,22 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
   }
 }
 
-size_t sv_lds_bytes(int bmax, int S) { return kRowsPerBlock * row_lds_bytes(bmax, S); }
+size_t sv_lds_bytes(int bmax, int S, int kpad) { return kRowsPerBlock * row_lds_bytes(bmax, S, kpad); }
 
-template <int MODE, int SV>
+template <int MODE, int SV, bool F16V>
 static hipError_t launch_mode(const SvArgs& a, int slots, int grid, size_t lds, hipStream_t st) {
   switch (slots) {
 #define MACE_CASE(SLV)                                                                   \
   case SLV: {                                                                            \
     static bool attr_set = false;                                                        \
     if (!attr_set) {                                                                     \
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel<SLV, MODE, SV>), \
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel<SLV, MODE, SV, F16V>), \
                                          hipFuncAttributeMaxDynamicSharedMemorySize,     \
                                          160 * 1024);                                    \
       if (e != hipSuccess) return e;                                                     \
       attr_set = true;                                                                   \
     }                                                                                    \
-    hipLaunchKernelGGL((sv_kernel<SLV, MODE, SV>), dim3(grid), dim3(kBlockThreads), lds, st, a); \
+    hipLaunchKernelGGL((sv_kernel<SLV, MODE, SV, F16V>), dim3(grid), dim3(kBlockThreads), lds, st, a); \
     break;                                                                               \
   }
     MACE_CASE(1)
@@ -467,18 +470,20 @@ static hipError_t launch_mode(const SvArgs& a, int slots, int grid, size_t lds, 
   return hipGetLastError();
 }
 
+template <int SV, bool F16V>
+static hipError_t launch_s(const SvArgs& a, int mode, int slots, int grid, size_t lds,
+                           hipStream_t st) {
+  if (mode == kSweep) return launch_mode<kSweep, SV, F16V>(a, slots, grid, lds, st);
+  if (mode == kTheta2) return launch_mode<kTheta2, SV, F16V>(a, slots, grid, lds, st);
+  return launch_mode<kRefresh, SV, F16V>(a, slots, grid, lds, st);
+}
+
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-  if (a.S == 4) {
-    if (mode == kSweep) return launch_mode<kSweep, 4>(a, slots, grid, lds, st);
-    if (mode == kTheta2) return launch_mode<kTheta2, 4>(a, slots, grid, lds, st);
-    return launch_mode<kRefresh, 4>(a, slots, grid, lds, st);
-  }
-  if (a.S == 8) {
-    if (mode == kSweep) return launch_mode<kSweep, 8>(a, slots, grid, lds, st);
-    if (mode == kTheta2) return launch_mode<kTheta2, 8>(a, slots, grid, lds, st);
-    return launch_mode<kRefresh, 8>(a, slots, grid, lds, st);
-  }
+  if (a.S == 4) return a.fp16 ? launch_s<4, true>(a, mode, slots, grid, lds, st)
+                              : launch_s<4, false>(a, mode, slots, grid, lds, st);
+  if (a.S == 8) return a.fp16 ? launch_s<8, true>(a, mode, slots, grid, lds, st)
+                              : launch_s<8, false>(a, mode, slots, grid, lds, st);
   return hipErrorInvalidValue;
 }
 
