@@ -42,6 +42,25 @@ def algorithmic_bytes_per_iter(nnz, N, n, K_rows_total):
     return nnz * 8 + N * n * 20 + K_rows_total * 12
 
 
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1911_09278_amd", "csrc", "mace_kernels.hip")
+    summ = os.path.join(ROOT, "profiles", "sv_kernel_scan512_hbm_counters.md")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        txt = open(summ).read()
+    except OSError:
+        return None
+    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", txt)
+    m_t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_h or not m_t or m_h.group(1) != h:
+        return None
+    return float(m_t.group(1))
+
+
 def cpu_baseline(g, cp, row, val, scan, va, w8, sigma, budget_s=20.0):
     """The FP64 oracle (as it stands) on a bounded sample: whole Mann iterations
     of the same scan, timed on this host."""
@@ -176,7 +195,7 @@ def main():
         "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
         "final_residual": info.residual,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "sv_kernel sweep", "avg_launch_us": avg_launch_s * 1e6,
                      "bytes_per_launch": bytes_launch},
     }
