@@ -42,15 +42,24 @@ def algorithmic_bytes_per_iter(nnz, N, n, K_rows_total):
     return nnz * 8 + N * n * 20 + K_rows_total * 12
 
 
+def kernel_source_hash(csrc):
+    """Short hash of the sweep kernel's sources (template header + units)."""
+    import hashlib
+    hh = hashlib.sha256()
+    for f in ("mace_internal.h", "mace_sweep.h", "mace_sweep_s8f32.hip"):
+        hh.update(open(os.path.join(csrc, f), "rb").read())
+    return hh.hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per sweep launch from the committed rocprofv3 counter summary,
     or None when the kernel source has changed since the counters were taken."""
     import hashlib
     import re
-    src = os.path.join(ROOT, "paper_1911_09278_amd", "csrc", "mace_kernels.hip")
+    csrc = os.path.join(ROOT, "paper_1911_09278_amd", "csrc")
     summ = os.path.join(ROOT, "profiles", "sv_kernel_scan512_hbm_counters.md")
     try:
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        h = kernel_source_hash(csrc)
         txt = open(summ).read()
     except OSError:
         return None

@@ -78,7 +78,8 @@ typedef struct {
   int32_t sv_size;        /* super-voxel side S in pixels: 4 or 8; 0 = 8 for
                              images of at least 256 x 256 pixels, else 4 */
   int32_t rows_per_agent; /* concurrent super-voxels per agent; 0 = automatic
-                             (about 4096 in total over the agents); 1 =
+                             (about 4096 in total over the agents, at most a
+                             quarter of one colour's super-voxels); 1 =
                              sequential (one super-voxel of an agent at a
                              time: the visiting order of mace_visit_order) */
   int32_t fp32_tail_iters;/* with precision 1: last iterations in FP32 A */

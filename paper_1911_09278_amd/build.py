@@ -1,39 +1,55 @@
-"""Build the HIP library (libmace.so) for gfx950 with hipcc, in-tree."""
+"""Build the HIP library (libmace.so) for gfx950 with hipcc, in-tree.
+
+Every translation unit is compiled to an object in parallel, then linked.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libmace.so")
-SOURCES = ["mace_host.cpp", "mace_kernels.hip"]
+SOURCES = ["mace_host.cpp", "mace_kernels.hip", "mace_sweep_s4f32.hip", "mace_sweep_s4f16.hip",
+           "mace_sweep_s8f32.hip", "mace_sweep_s8f16.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
-         # packed FP32 VALU ops stay off (hardware notes)
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+         # packed FP32 VALU ops stay off (hardware note in the design doc)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
 
 
+def _compile(src: str) -> str:
+    obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
+        raise RuntimeError(f"hipcc failed on {src}")
+    return obj
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    srcs = []
-    for f in SOURCES:
-        p = os.path.join(CSRC, f)
-        srcs += ["-x", "hip", p]
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp, "-lpthread"]
+    cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-fPIC"] + objs + ["-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
+        raise RuntimeError("link failed")
     os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 

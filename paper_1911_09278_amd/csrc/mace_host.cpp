@@ -540,12 +540,14 @@ static Schedule* get_schedule(mace_system* s, int only_agent, int P) {
 }
 
 // Concurrent super-voxels per agent: enough 16-lane rows in total (about
-// 4096, i.e. 1024 waves) to keep every CU busy, at most the SVs of one colour.
+// 4096, i.e. 1024 waves) to keep every CU busy, but at most a quarter of the
+// SVs of one colour (updating a whole colour at once is block Jacobi, which
+// loses stability on small images).
 static int default_rows_per_agent(const mace_system* s) {
   if (s->rows_per_agent > 0) return s->rows_per_agent;
   const int per_colour = (s->n_sv + 3) / 4;
   const int P = (4096 + s->N - 1) / s->N;
-  return std::max(1, std::min(P, per_colour));
+  return std::max(1, std::min(P, per_colour / 4));
 }
 
 // ---------------------------------------------------------------- workspace

@@ -1,5 +1,6 @@
 // Internal declarations shared by the host runtime and the HIP kernels.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -57,6 +58,12 @@ struct SvArgs {
   int fp16;             // read the FP16 records
   int strict;           // one SV of an agent at a time: stage e after the previous flush
 };
+
+// Per-variant sweep launchers (mace_sweep_*.hip).
+hipError_t launch_sv_s4f32(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
+hipError_t launch_sv_s4f16(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
+hipError_t launch_sv_s8f32(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
+hipError_t launch_sv_s8f16(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
 
 // Launchers (defined in mace_kernels.hip).
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);

@@ -1,0 +1,9 @@
+// Instantiation unit: super-voxel side 8, FP16 records.
+#include "mace_sweep.h"
+
+namespace mace {
+hipError_t launch_sv_s8f16(const SvArgs& a, int mode, int slots, int grid, size_t lds,
+                          hipStream_t st) {
+  return launch_s<8, true>(a, mode, slots, grid, lds, st);
+}
+}  // namespace mace

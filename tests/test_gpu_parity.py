@@ -131,6 +131,29 @@ def test_concurrent_qggmrf_fixed_point(m):
     assert _nrmse(x, ref["x"]) <= 1e-4, _nrmse(x, ref["x"])
 
 
+def test_fp16_matrix_fixed_point_and_fp32_tail(m):
+    """FP16 matrix values with a per-(agent, pixel) scale: the fixed point is
+    within 1e-3 of the oracle's; with the last iterations in FP32 (after an
+    error-sinogram refresh) within 1e-4."""
+    g = mi.Geometry(40, 40, 96, 60)
+    N, sx, sigma = 4, 0.0015, 0.001
+    (cp, row, val), s, va, O = _setup(g, 17, N, 1, sx, 1.2)
+    ref = O.mace_solve(0.8, sigma, 20000, tol=1e-12, relax=0.5)
+    prior = m.make_prior(1, sx, 2.0, 1.2, 1.0)
+    h = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, precision=1)
+    h.set_relaxation(0.5)
+    x16, info = h.solve(s.y, s.lam, prior, 0.8, sigma, 1500)
+    print("fp16 nrmse", _nrmse(x16, ref["x"]), "resid", info.residual, flush=True)
+    assert _nrmse(x16, ref["x"]) <= 1e-3
+    t = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, precision=1,
+                 fp32_tail_iters=300)
+    t.set_relaxation(0.5)
+    xt, info = t.solve(s.y, s.lam, prior, 0.8, sigma, 1800)
+    print("fp16 + fp32 tail nrmse", _nrmse(xt, ref["x"]), "resid", info.residual, flush=True)
+    assert _nrmse(xt, ref["x"]) <= 1e-4
+    assert t.matrix_bytes > h.matrix_bytes  # the tail keeps the FP32 values too
+
+
 def test_error_sinogram_and_consensus_invariants(m):
     g = mi.Geometry(48, 48, 96, 72)
     N = 4
