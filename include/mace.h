@@ -26,10 +26,12 @@
  *   - All host pointers are read only during the call and stay owned by the
  *     caller; outputs go to caller buffers.  A mace_system owns its device
  *     memory until mace_free_system().  Calls on one mace_system must not
- *     overlap (the system holds one scan workspace).
+ *     overlap (the system holds the scan workspaces and runs every solve on
+ *     one private stream).
  *   - Device-pointer variants (suffix _dev) take device addresses and a HIP
  *     stream (hipStream_t passed as void*, NULL = default stream); they
- *     enqueue work on that stream and return after it has finished.
+ *     wait for the work already queued on that stream, run on the system's
+ *     own stream, and return after it has finished.
  */
 #ifndef MACE_H
 #define MACE_H
@@ -136,6 +138,33 @@ int mace_solve_dev(mace_system* sys, const float* y, const float* lambda,
                    mace_info* info, void* stream);
 
 /*
+ * Batched partial-update MACE: n_scans independent scans of this geometry
+ * (e.g. the slices of a volume, or requests of a reconstruction service)
+ * advance together, one Mann iteration of every scan per round of kernel
+ * launches, all scans sharing the one device copy of the matrix (Sec. I: the
+ * precomputed matrix is the large, reused operand).  Each scan stops on its
+ * own: when its residual falls below tol it is switched off while the others
+ * continue.  y[i], lambda[i]: [n_views * n_channels] of scan i; x_out[i]:
+ * [nx*ny]; info (optional): array of n_scans records.  1 <= n_scans <= 128.
+ * With rows_per_agent = 1 every scan follows exactly the iterates mace_solve
+ * computes for it alone.  With the automatic rows_per_agent the concurrent
+ * super-voxels per (scan, agent) are divided by n_scans, so the total
+ * concurrency stays about the same; the scans then reach the same fixed
+ * points by different iterates.  Returns the worst status over the scans.
+ */
+int mace_solve_batch(mace_system* sys, int32_t n_scans, const float* const* y,
+                     const float* const* lambda, const mace_prior* prior, double rho,
+                     double sigma, int32_t sweeps, int32_t max_iters, double tol,
+                     float* const* x_out, mace_info* info);
+
+/* Device-pointer variant of mace_solve_batch (every y/lambda/x_out array in
+ * device memory; the pointer arrays themselves on the host). */
+int mace_solve_batch_dev(mace_system* sys, int32_t n_scans, const float* const* y,
+                         const float* const* lambda, const mace_prior* prior, double rho,
+                         double sigma, int32_t sweeps, int32_t max_iters, double tol,
+                         float* const* x_out, mace_info* info, void* stream);
+
+/*
  * Partial proximal update of one agent (Algorithm 2 applied `sweeps` times):
  * starting from x_init, ICD passes on f_i(z) + ||z - v||^2/(2 sigma^2)
  * (eq. (prox_F)); with many sweeps this approaches F_i(v).  All image arrays
@@ -153,8 +182,9 @@ int mace_prox(mace_system* sys, int32_t agent, const float* y, const float* lamb
  */
 int mace_visit_order(const mace_system* sys, int64_t* order);
 
-/* Stacked agent states of the last solve (device layout [N][nx*ny], copied to
- * host): w and X (either may be NULL). */
+/* Stacked agent states of the last solve (of the first scan of the last
+ * batch), device layout [N][nx*ny], copied to host: w and X (either may be
+ * NULL). */
 int mace_get_state(const mace_system* sys, float* w, float* X);
 
 /* Error sinogram e = y - A X_i of the last solve, every row from its own

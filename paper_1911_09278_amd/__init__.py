@@ -68,6 +68,10 @@ def _load():
     L.mace_solve.restype = ctypes.c_int
     L.mace_solve_dev.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, P(Info), vp]
     L.mace_solve_dev.restype = ctypes.c_int
+    L.mace_solve_batch.argtypes = [vp, i32, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp]
+    L.mace_solve_batch.restype = ctypes.c_int
+    L.mace_solve_batch_dev.argtypes = [vp, i32, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, vp]
+    L.mace_solve_batch_dev.restype = ctypes.c_int
     L.mace_prox.argtypes = [vp, i32, vp, vp, P(Prior), d, vp, vp, i32, vp]
     L.mace_prox.restype = ctypes.c_int
     L.mace_visit_order.argtypes = [vp, vp]
@@ -94,7 +98,8 @@ def _load():
 _lib = _load()
 
 # Entry points of the C ABI, by name.
-EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_dev", "mace_prox", "mace_visit_order",
+EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_dev", "mace_solve_batch",
+            "mace_solve_batch_dev", "mace_prox", "mace_visit_order",
             "mace_get_state", "mace_get_error_sinogram", "mace_system_bytes", "mace_check_layout", "mace_set_timing",
             "mace_set_relaxation",
             "mace_free_system", "mace_last_error")
@@ -200,6 +205,41 @@ class System:
                                  None if stream_ptr is None else ctypes.c_void_p(stream_ptr))
         _check(rc)
         return info
+
+    def solve_batch(self, ys, lams, prior: Prior, rho, sigma, max_iters, tol=0.0, sweeps=1):
+        """Several scans of this geometry at once (host arrays); returns
+        (list of x, list of info)."""
+        n = len(ys)
+        if n != len(lams) or n == 0:
+            raise ValueError("need one lambda per y and at least one scan")
+        yy = [np.ascontiguousarray(y, dtype=np.float32) for y in ys]
+        ll = [np.ascontiguousarray(l, dtype=np.float32) for l in lams]
+        if any(a.size != self.n_rows for a in yy + ll):
+            raise ValueError("y / lambda have the wrong size")
+        xs = [np.empty(self.n, dtype=np.float32) for _ in range(n)]
+        arr = ctypes.c_void_p * n
+        infos = (Info * n)()
+        rc = _lib.mace_solve_batch(self._h, n, arr(*[a.ctypes.data for a in yy]),
+                                   arr(*[a.ctypes.data for a in ll]), ctypes.byref(prior),
+                                   float(rho), float(sigma), int(sweeps), int(max_iters),
+                                   float(tol), arr(*[a.ctypes.data for a in xs]), infos)
+        _check(rc)
+        return xs, list(infos)
+
+    def solve_batch_dev(self, y_ptrs, lam_ptrs, prior: Prior, rho, sigma, max_iters, x_ptrs,
+                        tol=0.0, sweeps=1, stream_ptr=None):
+        """Device pointers per scan; returns the list of info records."""
+        n = len(y_ptrs)
+        if n != len(lam_ptrs) or n != len(x_ptrs) or n == 0:
+            raise ValueError("need matching, non-empty pointer lists")
+        arr = ctypes.c_void_p * n
+        infos = (Info * n)()
+        rc = _lib.mace_solve_batch_dev(self._h, n, arr(*y_ptrs), arr(*lam_ptrs),
+                                       ctypes.byref(prior), float(rho), float(sigma), int(sweeps),
+                                       int(max_iters), float(tol), arr(*x_ptrs), infos,
+                                       None if stream_ptr is None else ctypes.c_void_p(stream_ptr))
+        _check(rc)
+        return list(infos)
 
     def prox(self, agent, y, lam, prior: Prior, sigma, v, x_init, sweeps=1):
         yy = np.ascontiguousarray(y, dtype=np.float32)

@@ -1,32 +1,26 @@
-// Host runtime of the MACE library: argument checks, repacking of the system
-// matrix into the device layout, super-voxel schedules, per-scan workspace
-// and the Mann-iteration driver.  The C ABI is declared in include/mace.h.
-#include <hip/hip_fp16.h>
-#include <hip/hip_runtime.h>
-
+// Host runtime of the MACE library, part 1: argument checks, repacking of the
+// system matrix into the device layout, super-voxel schedules, and the
+// system-level entry points of the C ABI (include/mace.h).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <map>
-#include <memory>
 #include <numeric>
 #include <random>
-#include <string>
 #include <thread>
-#include <vector>
+#include <tuple>
 
-#include "../../include/mace.h"
-#include "mace_internal.h"
+#include "mace_runtime.h"
 
 using namespace mace;
 
 // ---------------------------------------------------------------- errors
 static thread_local std::string g_err;
 
-static int fail(int code, const char* fmt, ...) {
+namespace mace {
+int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -35,89 +29,16 @@ static int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
-
-#define HIP_OK(expr)                                                                   \
-  do {                                                                                 \
-    hipError_t _e = (expr);                                                            \
-    if (_e != hipSuccess)                                                              \
-      return fail(_e == hipErrorOutOfMemory ? MACE_E_NOMEM : MACE_E_HIP, "%s: %s (%s:%d)", \
-                  #expr, hipGetErrorString(_e), __FILE__, __LINE__);                   \
-  } while (0)
+const std::string& last_error_text() { return g_err; }
+}  // namespace mace
 
 extern "C" const char* mace_last_error(void) { return g_err.c_str(); }
 
-// ---------------------------------------------------------------- device buffers
-template <class T>
-struct DevBuf {
-  T* p = nullptr;
-  size_t count = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  ~DevBuf() { reset(); }
-  void reset() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    count = 0;
-  }
-  hipError_t alloc(size_t n) {
-    reset();
-    count = n;
-    if (n == 0) return hipSuccess;
-    return hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
-  }
-  hipError_t upload(const T* h, size_t n) {
-    hipError_t e = alloc(n);
-    if (e != hipSuccess || n == 0) return e;
-    return hipMemcpy(p, h, n * sizeof(T), hipMemcpyHostToDevice);
-  }
-  size_t bytes() const { return count * sizeof(T); }
-};
-
-// ---------------------------------------------------------------- system
-struct Schedule {
-  DevBuf<int> tasks[4];  // one table per colour phase: [R][T]
-  int R = 0, T[4] = {0, 0, 0, 0}, grid = 0;
-};
-
-struct mace_system {
-  int nx = 0, ny = 0, n = 0, n_views = 0, n_ch = 0, N = 0;
-  int Kmax = 0, slots = 0, kpad = 0;
-  int S = 4, gx = 0, gy = 0, n_sv = 0;
-  int bmax = 0;
-  int wmax = 0;
-  int precision = 0;
-  int rows_per_agent = 0;
-  int fp32_tail = 0;
-  int refresh_every = 0;
-  int64_t estride = 0;
-  std::vector<int> view_agent;             // [n_views]
-  std::vector<std::vector<int>> views;     // agent -> its views, ascending
-  std::vector<int> sv_pix0;                // [n_sv + 1]
-  std::vector<int> colour_svs[4];          // SVs of each colour in schedule order
-  // device copies of the matrix
-  DevBuf<float2> aval;
-  DevBuf<__half2> hval;
-  DevBuf<float> hscale;
-  DevBuf<uint16_t> aoff;
-  DevBuf<BandEnt> band;
-  DevBuf<int> band_rows;
-  DevBuf<int> d_sv_pix0;
-  DevBuf<int> row_src;                     // agent-block row -> global row (or -1)
-  std::map<int64_t, std::unique_ptr<Schedule>> schedules;
-  // scan workspace
-  DevBuf<float> e, lam, yb, X, w, wbar, th2;
-  DevBuf<double> part, resid;
-  DevBuf<int> counter;
-  int resid_cap = 0, part_cap = 0;
-  int64_t matrix_bytes = 0;
-  bool timing = false;
-  double relax = 0.0;  // 0: automatic (1 for the sequential schedule, 0.5 otherwise)
-  std::vector<hipEvent_t> ev;  // timing events, created on demand
-  ~mace_system() {
-    for (auto e : ev) (void)hipEventDestroy(e);
-  }
-};
+mace_system::~mace_system() {
+  graphs.clear();
+  for (auto e : ev) (void)hipEventDestroy(e);
+  if (stream) (void)hipStreamDestroy(stream);
+}
 
 // ---------------------------------------------------------------- repacking
 static int build_partition(mace_system* s, const int32_t* view_to_agent) {
@@ -438,6 +359,10 @@ static int check_pack(const mace_system* s, const HostPack& hp) {
     }
   }
   if (s->sv_pix0[s->n_sv] != s->n) return fail(MACE_E_MATRIX, "check: SVs do not tile the image");
+  const int wm = s->S <= 4 ? 8 : 16;
+  if (s->wmax > wm)
+    return fail(MACE_E_MATRIX, "a super-voxel's band spans %d channels of one view (at most %d); use sv_size 4",
+                s->wmax, wm);
   return MACE_OK;
 }
 
@@ -450,37 +375,46 @@ struct HostSchedule {
   std::vector<int> tab[4];
 };
 
-static void build_schedule(const mace_system* s, int only_agent, int P, HostSchedule& hs) {
+// Rows of 16 lanes are grouped 16 to a workgroup; workgroups are dispatched
+// round-robin over the 8 XCDs. The rows serving agent a (of every slot) are
+// placed in workgroups of XCD a mod 8, so the agent's sinogram blocks and its
+// matrix records stay in one L2; all slots walk the SVs in the same order, so
+// the same records are read by several slots at about the same time.
+static void build_schedule(const mace_system* s, int n_slots, int only_agent, int P,
+                           HostSchedule& hs) {
   std::vector<int> agents;
   if (only_agent >= 0)
     agents.push_back(only_agent);
   else
     for (int a = 0; a < s->N; ++a) agents.push_back(a);
+  struct RowId {
+    int slot, agent, rank;
+  };
   const int nxcd = 8;
-  std::vector<std::vector<std::pair<int, int>>> xrows(nxcd);  // (agent, rank within agent)
-  for (size_t i = 0; i < agents.size(); ++i) {
-    const int x = (int)(i % nxcd);
-    for (int r = 0; r < P; ++r) xrows[x].push_back({agents[i], r});
-  }
-  int wg_per_xcd = 0;
-  for (int x = 0; x < nxcd; ++x)
+  std::vector<std::vector<RowId>> xrows(nxcd);
+  for (int sl = 0; sl < n_slots; ++sl)
+    for (size_t i = 0; i < agents.size(); ++i)
+      for (int r = 0; r < P; ++r) xrows[agents[i] % nxcd].push_back({sl, agents[i], r});
+  int wg_per_xcd = 0, used = 0;
+  for (int x = 0; x < nxcd; ++x) {
     wg_per_xcd = std::max<int>(wg_per_xcd, (int)((xrows[x].size() + kRowsPerBlock - 1) / kRowsPerBlock));
-  std::vector<std::pair<int, int>> row_of;  // global row -> (agent, rank) or (-1, -1)
-  if (agents.size() >= (size_t)nxcd) {
+    used += !xrows[x].empty();
+  }
+  std::vector<RowId> row_of;
+  if (used == nxcd) {
     hs.grid = wg_per_xcd * nxcd;
-    row_of.assign((size_t)hs.grid * kRowsPerBlock, {-1, -1});
+    row_of.assign((size_t)hs.grid * kRowsPerBlock, {-1, -1, -1});
     for (int x = 0; x < nxcd; ++x)
       for (size_t q = 0; q < xrows[x].size(); ++q) {
         const int u = (int)(q / kRowsPerBlock), j = (int)(q % kRowsPerBlock);
         row_of[(size_t)(u * nxcd + x) * kRowsPerBlock + j] = xrows[x][q];
       }
   } else {
-    // fewer agents than XCDs: pack the rows densely
-    std::vector<std::pair<int, int>> all;
-    for (int a : agents)
-      for (int r = 0; r < P; ++r) all.push_back({a, r});
+    // some XCDs would stay idle: pack the rows densely instead
+    std::vector<RowId> all;
+    for (int x = 0; x < nxcd; ++x) all.insert(all.end(), xrows[x].begin(), xrows[x].end());
     hs.grid = (int)((all.size() + kRowsPerBlock - 1) / kRowsPerBlock);
-    row_of.assign((size_t)hs.grid * kRowsPerBlock, {-1, -1});
+    row_of.assign((size_t)hs.grid * kRowsPerBlock, {-1, -1, -1});
     for (size_t q = 0; q < all.size(); ++q) row_of[q] = all[q];
   }
   hs.R = hs.grid * kRowsPerBlock;
@@ -490,43 +424,51 @@ static void build_schedule(const mace_system* s, int only_agent, int P, HostSche
     hs.T[c] = T;
     hs.tab[c].assign((size_t)hs.R * std::max(T, 1), -1);
     for (int r = 0; r < hs.R; ++r) {
-      const int a = row_of[r].first, rank = row_of[r].second;
-      if (a < 0) continue;
+      const RowId id = row_of[r];
+      if (id.agent < 0) continue;
       for (int t = 0; t < T; ++t) {
-        const size_t q = (size_t)t * P + rank;
-        if (q < L.size()) hs.tab[c][(size_t)r * T + t] = a * s->n_sv + L[q];
+        const size_t q = (size_t)t * P + id.rank;
+        if (q < L.size())
+          hs.tab[c][(size_t)r * T + t] = (id.slot << kSlotShift) | (id.agent * s->n_sv + L[q]);
       }
     }
   }
 }
 
-// Every (agent, SV) of the scheduled agents appears exactly once per pass,
-// in the phase of its colour, and every task id is in range.
-static int check_schedule(const mace_system* s, int only_agent, const HostSchedule& hs) {
-  std::vector<int> seen((size_t)s->N * s->n_sv, 0);
+// Every (slot, agent, SV) of the scheduled agents appears exactly once per
+// pass, in the phase of its colour, and every task id is in range.
+static int check_schedule(const mace_system* s, int n_slots, int only_agent, const HostSchedule& hs) {
+  const size_t per_slot = (size_t)s->N * s->n_sv;
+  if (per_slot >= ((size_t)1 << kSlotShift)) return fail(MACE_E_ARG, "check: too many (agent, SV) pairs");
+  if (n_slots > kMaxScanSlots) return fail(MACE_E_ARG, "check: too many slots");
+  std::vector<int> seen(per_slot * n_slots, 0);
   for (int c = 0; c < 4; ++c)
     for (int t : hs.tab[c]) {
       if (t < 0) continue;
-      if (t >= s->N * s->n_sv) return fail(MACE_E_ARG, "check: task id out of range");
-      const int sv = t % s->n_sv;
+      const int slot = t >> kSlotShift, local = t & ((1 << kSlotShift) - 1);
+      if (slot >= n_slots || (size_t)local >= per_slot) return fail(MACE_E_ARG, "check: task id out of range");
+      const int sv = local % s->n_sv;
       if (((sv % s->gx) & 1) + 2 * ((sv / s->gx) & 1) != c) return fail(MACE_E_ARG, "check: task in the wrong colour phase");
-      seen[t]++;
+      seen[(size_t)slot * per_slot + local]++;
     }
-  for (int a = 0; a < s->N; ++a)
-    for (int sv = 0; sv < s->n_sv; ++sv) {
-      const int want = (only_agent < 0 || only_agent == a) ? 1 : 0;
-      if (seen[(size_t)a * s->n_sv + sv] != want) return fail(MACE_E_ARG, "check: task visited %d times", seen[(size_t)a * s->n_sv + sv]);
-    }
+  for (int sl = 0; sl < n_slots; ++sl)
+    for (int a = 0; a < s->N; ++a)
+      for (int sv = 0; sv < s->n_sv; ++sv) {
+        const int want = (only_agent < 0 || only_agent == a) ? 1 : 0;
+        const int got = seen[(size_t)sl * per_slot + (size_t)a * s->n_sv + sv];
+        if (got != want) return fail(MACE_E_ARG, "check: task visited %d times", got);
+      }
   return MACE_OK;
 }
 
-static Schedule* get_schedule(mace_system* s, int only_agent, int P) {
-  const int64_t key = ((int64_t)(only_agent + 1) << 32) | (uint32_t)P;
+namespace mace {
+Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P) {
+  const auto key = std::make_tuple(n_slots, only_agent, P);
   auto it = s->schedules.find(key);
   if (it != s->schedules.end()) return it->second.get();
   HostSchedule hs;
-  build_schedule(s, only_agent, P, hs);
-  if (check_schedule(s, only_agent, hs)) return nullptr;
+  build_schedule(s, n_slots, only_agent, P, hs);
+  if (check_schedule(s, n_slots, only_agent, hs)) return nullptr;
   auto sch = std::make_unique<Schedule>();
   sch->grid = hs.grid;
   sch->R = hs.R;
@@ -543,41 +485,17 @@ static Schedule* get_schedule(mace_system* s, int only_agent, int P) {
 // 4096, i.e. 1024 waves) to keep every CU busy, but at most a quarter of the
 // SVs of one colour (updating a whole colour at once is block Jacobi, which
 // loses stability on small images).
-static int default_rows_per_agent(const mace_system* s) {
+int default_rows_per_agent(const mace_system* s) {
   if (s->rows_per_agent > 0) return s->rows_per_agent;
   const int per_colour = (s->n_sv + 3) / 4;
   const int P = (4096 + s->N - 1) / s->N;
   return std::max(1, std::min(P, per_colour / 4));
 }
+}  // namespace mace
 
-// ---------------------------------------------------------------- workspace
-static int ensure_workspace(mace_system* s, int max_iters, int R) {
-  const size_t nimg = (size_t)s->N * s->n;
-  const size_t nrow = (size_t)s->N * s->estride;
-  if (s->e.count != nrow) {
-    HIP_OK(s->e.alloc(nrow));
-    HIP_OK(s->lam.alloc(nrow));
-    HIP_OK(s->yb.alloc(nrow));
-    HIP_OK(s->X.alloc(nimg));
-    HIP_OK(s->w.alloc(nimg));
-    HIP_OK(s->th2.alloc(nimg));
-    HIP_OK(s->wbar.alloc(s->n));
-    HIP_OK(s->counter.alloc(1));
-  }
-  const int pc = 4 * R;
-  if (s->part_cap < pc) {
-    HIP_OK(s->part.alloc((size_t)pc * 4));
-    s->part_cap = pc;
-  }
-  if (s->resid_cap < max_iters) {
-    HIP_OK(s->resid.alloc((size_t)std::max(1, max_iters)));
-    s->resid_cap = std::max(1, max_iters);
-  }
-  return MACE_OK;
-}
-
-static void fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, double rho,
-                      double sigma, bool fp16) {
+// ---------------------------------------------------------------- kernel arguments
+void mace::fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, double rho,
+                     double sigma, bool fp16) {
   memset(&a, 0, sizeof a);
   a.nx = s->nx;
   a.ny = s->ny;
@@ -597,12 +515,7 @@ static void fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, dou
   a.band = s->band.p;
   a.band_rows = s->band_rows.p;
   a.estride = s->estride;
-  a.e = s->e.p;
-  a.lam = s->lam.p;
-  a.X = s->X.p;
-  a.w = s->w.p;
-  a.wbar = s->wbar.p;
-  a.th2 = s->th2.p;
+  a.slots = s->table.p;
   a.invN = (float)(1.0 / s->N);
   a.relax = (float)(s->relax > 0.0 ? s->relax : (default_rows_per_agent(s) == 1 ? 1.0 : 0.5));
   a.rho = (float)rho;
@@ -620,7 +533,7 @@ static void fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, dou
   }
 }
 
-static int check_prior(const mace_prior* pr) {
+int mace::check_prior(const mace_prior* pr) {
   if (!pr) return fail(MACE_E_ARG, "prior is NULL");
   if (pr->kind != 0 && pr->kind != 1) return fail(MACE_E_ARG, "prior kind %d unknown", pr->kind);
   if (!(pr->sigma_x > 0) || !std::isfinite(pr->sigma_x)) return fail(MACE_E_ARG, "sigma_x must be > 0");
@@ -683,6 +596,7 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
   if (sv_lds_bytes(s->bmax, s->S, s->kpad) > 160 * 1024)
     return fail(MACE_E_ARG, "super-voxel band needs %zu bytes of LDS per workgroup; use a smaller sv_size",
                 sv_lds_bytes(s->bmax, s->S, s->kpad));
+  HIP_OK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
   *out = s.release();
   g_err.clear();
   return MACE_OK;
@@ -725,10 +639,12 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
   const int P = default_rows_per_agent(&s);
   for (int only = -1; only < s.N; ++only) {
     for (int PP : {1, P}) {
-      HostSchedule hs;
-      build_schedule(&s, only, PP, hs);
-      rc = check_schedule(&s, only, hs);
-      if (rc) return rc;
+      for (int ns : {1, 3}) {
+        HostSchedule hs;
+        build_schedule(&s, ns, only, PP, hs);
+        rc = check_schedule(&s, ns, only, hs);
+        if (rc) return rc;
+      }
     }
     if (only >= 2) break;
   }
@@ -767,259 +683,3 @@ extern "C" int mace_visit_order(const mace_system* s, int64_t* order) {
   return MACE_OK;
 }
 
-extern "C" int mace_get_state(const mace_system* s, float* w, float* X) {
-  if (!s) return fail(MACE_E_ARG, "NULL system");
-  if (!s->w.p) return fail(MACE_E_ARG, "no solve has run on this system");
-  const size_t bytes = (size_t)s->N * s->n * sizeof(float);
-  if (w) HIP_OK(hipMemcpy(w, s->w.p, bytes, hipMemcpyDeviceToHost));
-  if (X) HIP_OK(hipMemcpy(X, s->X.p, bytes, hipMemcpyDeviceToHost));
-  return MACE_OK;
-}
-
-extern "C" int mace_get_error_sinogram(const mace_system* s, float* e) {
-  if (!s || !e) return fail(MACE_E_ARG, "NULL argument");
-  if (!s->e.p) return fail(MACE_E_ARG, "no solve has run on this system");
-  std::vector<float> blk(s->e.count);
-  HIP_OK(hipMemcpy(blk.data(), s->e.p, s->e.bytes(), hipMemcpyDeviceToHost));
-  for (int a = 0; a < s->N; ++a)
-    for (size_t kl = 0; kl < s->views[a].size(); ++kl)
-      memcpy(e + (size_t)s->views[a][kl] * s->n_ch, blk.data() + (size_t)a * s->estride + kl * s->n_ch,
-             sizeof(float) * s->n_ch);
-  return MACE_OK;
-}
-
-// Load y / Lambda (device, global row order) into the agent blocks and set the
-// initial state: w = w_init (or 0), X = G(w), e = y - A X, theta2.
-static int start_scan(mace_system* s, const float* y, const float* lam, const float* w_init,
-                      const mace_prior* pr, double sigma, bool fp16, hipStream_t st) {
-  const int64_t nrow = (int64_t)s->N * s->estride;
-  HIP_OK(launch_gather_rows(s->yb.p, y, s->row_src.p, nrow, st));
-  HIP_OK(launch_copy(s->e.p, s->yb.p, nrow, st));
-  HIP_OK(launch_gather_rows(s->lam.p, lam, s->row_src.p, nrow, st));
-  const int64_t nimg = (int64_t)s->N * s->n;
-  if (w_init)
-    HIP_OK(launch_copy(s->w.p, w_init, nimg, st));
-  else
-    HIP_OK(launch_fill(s->w.p, 0.f, nimg, st));
-  HIP_OK(launch_broadcast_mean(s->w.p, s->wbar.p, s->X.p, s->N, s->n, st));
-  const int P = default_rows_per_agent(s);
-  Schedule* sch = get_schedule(s, -1, P);
-  if (!sch) return fail(MACE_E_HIP, "schedule upload failed");
-  SvArgs a;
-  fill_args(s, a, pr, 0.8, sigma, fp16);
-  a.R = sch->R;
-  a.strict = P == 1 ? 1 : 0;
-  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
-  for (int c = 0; c < 4; ++c) {
-    a.tasks = sch->tasks[c].p;
-    a.T = sch->T[c];
-    HIP_OK(launch_sv(a, kTheta2, s->slots, sch->grid, lds, st));
-    if (w_init) HIP_OK(launch_sv(a, kRefresh, s->slots, sch->grid, lds, st));
-  }
-  return MACE_OK;
-}
-
-static int solve_impl(mace_system* s, const float* y, const float* lam, const mace_prior* pr,
-                      double rho, double sigma, int sweeps, int max_iters, double tol,
-                      const float* w_init, float* x_out, mace_info* info, hipStream_t st) {
-  int rc = check_prior(pr);
-  if (rc) return rc;
-  if (!(rho > 0 && rho < 1)) return fail(MACE_E_ARG, "rho must be in (0, 1)");
-  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(MACE_E_ARG, "sigma must be > 0");
-  if (sweeps < 1) return fail(MACE_E_ARG, "sweeps must be >= 1");
-  if (max_iters < 0) return fail(MACE_E_ARG, "max_iters must be >= 0");
-  const int P = default_rows_per_agent(s);
-  Schedule* sch = get_schedule(s, -1, P);
-  if (!sch) return fail(MACE_E_HIP, "schedule upload failed");
-  rc = ensure_workspace(s, max_iters, sch->R);
-  if (rc) return rc;
-  const bool fp16 = s->precision == 1;
-  rc = start_scan(s, y, lam, w_init, pr, sigma, fp16, st);
-  if (rc) return rc;
-  HIP_OK(hipMemsetAsync(s->counter.p, 0, sizeof(int), st));
-  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
-  SvArgs a;
-  fill_args(s, a, pr, rho, sigma, fp16);
-  a.R = sch->R;
-  a.strict = P == 1 ? 1 : 0;
-  std::vector<double> hres(std::max(1, max_iters));
-  // timing: one event pair around the sweep launches of each iteration, one
-  // pair around the whole loop
-  const bool timing = s->timing;
-  if (timing && (int)s->ev.size() < 2 * max_iters + 2) {
-    for (auto e : s->ev) (void)hipEventDestroy(e);
-    s->ev.assign(2 * max_iters + 2, nullptr);
-    for (auto& e : s->ev) HIP_OK(hipEventCreate(&e));
-  }
-  if (timing) HIP_OK(hipEventRecord(s->ev[2 * max_iters], st));
-  int it = 0;
-  int status = MACE_OK;
-  double last = 0.0;
-  const int check_every = tol > 0 ? 1 : 0;
-  bool refreshed = false;
-  for (; it < max_iters; ++it) {
-    if (fp16 && s->fp32_tail > 0 && !refreshed && it >= max_iters - s->fp32_tail) {
-      // switch to FP32 A values: rebuild e = y - A X and theta2 with them
-      a.fp16 = 0;
-      refreshed = true;
-      HIP_OK(launch_copy(s->e.p, s->yb.p, (int64_t)s->N * s->estride, st));
-      for (int c = 0; c < 4; ++c) {
-        a.tasks = sch->tasks[c].p;
-        a.T = sch->T[c];
-        HIP_OK(launch_sv(a, kTheta2, s->slots, sch->grid, lds, st));
-        HIP_OK(launch_sv(a, kRefresh, s->slots, sch->grid, lds, st));
-      }
-    }
-    if (s->refresh_every > 0 && it > 0 && it % s->refresh_every == 0 && !refreshed) {
-      // rebuild e = y - A X_i from the agent states (FP32 drift of the
-      // incrementally updated error sinogram)
-      HIP_OK(launch_copy(s->e.p, s->yb.p, (int64_t)s->N * s->estride, st));
-      for (int c = 0; c < 4; ++c) {
-        a.tasks = sch->tasks[c].p;
-        a.T = sch->T[c];
-        HIP_OK(launch_sv(a, kRefresh, s->slots, sch->grid, lds, st));
-      }
-    }
-    if (timing) HIP_OK(hipEventRecord(s->ev[2 * it], st));
-    for (int sw = 0; sw < sweeps; ++sw) {
-      a.mann = (sw == sweeps - 1) ? 1 : 0;
-      for (int c = 0; c < 4; ++c) {
-        a.tasks = sch->tasks[c].p;
-        a.T = sch->T[c];
-        a.part = s->part.p + (size_t)c * sch->R * 4;
-        HIP_OK(launch_sv(a, kSweep, s->slots, sch->grid, lds, st));
-      }
-    }
-    if (timing) HIP_OK(hipEventRecord(s->ev[2 * it + 1], st));
-    HIP_OK(launch_epilogue(s->w.p, s->wbar.p, s->N, s->n, s->part.p, 4 * sch->R, s->resid.p,
-                           s->counter.p, max_iters, st));
-    if (check_every) {
-      HIP_OK(hipMemcpyAsync(&last, s->resid.p + it, sizeof(double), hipMemcpyDeviceToHost, st));
-      HIP_OK(hipStreamSynchronize(st));
-      if (!std::isfinite(last)) {
-        status = MACE_E_NONFINITE;
-        ++it;
-        break;
-      }
-      if (last < tol) {
-        ++it;
-        break;
-      }
-    }
-  }
-  if (timing) HIP_OK(hipEventRecord(s->ev[2 * max_iters + 1], st));
-  HIP_OK(hipStreamSynchronize(st));
-  double sweep_ms = 0.0, iter_ms = 0.0;
-  if (timing) {
-    for (int k = 0; k < it; ++k) {
-      float ms = 0.f;
-      HIP_OK(hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]));
-      sweep_ms += ms;
-    }
-    float ms = 0.f;
-    HIP_OK(hipEventElapsedTime(&ms, s->ev[2 * max_iters], s->ev[2 * max_iters + 1]));
-    iter_ms = ms;
-  }
-  if (it > 0) {
-    HIP_OK(hipMemcpy(hres.data(), s->resid.p, sizeof(double) * it, hipMemcpyDeviceToHost));
-    last = hres[it - 1];
-    if (!std::isfinite(last)) status = MACE_E_NONFINITE;
-  }
-  if (status == MACE_OK && tol > 0 && !(last < tol)) status = MACE_W_MAXITER;
-  // x = mean_i w_i: wbar already holds it after the last epilogue
-  if (max_iters == 0) HIP_OK(launch_broadcast_mean(s->w.p, s->wbar.p, s->X.p, s->N, s->n, st));
-  HIP_OK(launch_copy(x_out, s->wbar.p, s->n, st));
-  HIP_OK(hipStreamSynchronize(st));
-  if (info) {
-    info->iters = it;
-    info->residual = last;
-    info->equits = (double)sweeps * it;
-    info->status = status;
-    info->sweep_ms = sweep_ms;
-    info->sweep_launches = timing ? it * sweeps * 4 : 0;
-    info->iter_ms = iter_ms;
-  }
-  if (status == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "non-finite residual at iteration %d", it);
-  return status;
-}
-
-extern "C" int mace_solve_dev(mace_system* s, const float* y, const float* lam,
-                              const mace_prior* pr, double rho, double sigma, int32_t sweeps,
-                              int32_t max_iters, double tol, const float* w_init, float* x_out,
-                              mace_info* info, void* stream) {
-  if (!s || !y || !lam || !x_out) return fail(MACE_E_ARG, "NULL argument");
-  return solve_impl(s, y, lam, pr, rho, sigma, sweeps, max_iters, tol, w_init, x_out, info,
-                    (hipStream_t)stream);
-}
-
-extern "C" int mace_solve(mace_system* s, const float* y, const float* lam, const mace_prior* pr,
-                          double rho, double sigma, int32_t sweeps, int32_t max_iters, double tol,
-                          const float* w_init, float* x_out, mace_info* info) {
-  if (!s || !y || !lam || !x_out) return fail(MACE_E_ARG, "NULL argument");
-  const size_t m = (size_t)s->n_views * s->n_ch, nimg = (size_t)s->N * s->n;
-  DevBuf<float> dy, dl, dw, dx;
-  HIP_OK(dy.upload(y, m));
-  HIP_OK(dl.upload(lam, m));
-  if (w_init) HIP_OK(dw.upload(w_init, nimg));
-  HIP_OK(dx.alloc(s->n));
-  int rc = solve_impl(s, dy.p, dl.p, pr, rho, sigma, sweeps, max_iters, tol,
-                      w_init ? dw.p : nullptr, dx.p, info, nullptr);
-  if (rc < 0 && rc != MACE_E_NONFINITE) return rc;
-  HIP_OK(hipMemcpy(x_out, dx.p, sizeof(float) * s->n, hipMemcpyDeviceToHost));
-  if (rc == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "%s", g_err.c_str());
-  return rc;
-}
-
-extern "C" int mace_prox(mace_system* s, int32_t agent, const float* y, const float* lam,
-                         const mace_prior* pr, double sigma, const float* v,
-                         const float* x_init, int32_t sweeps, float* x_out) {
-  if (!s || !y || !lam || !v || !x_init || !x_out) return fail(MACE_E_ARG, "NULL argument");
-  if (agent < 0 || agent >= s->N) return fail(MACE_E_ARG, "agent %d out of range", agent);
-  int rc = check_prior(pr);
-  if (rc) return rc;
-  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(MACE_E_ARG, "sigma must be > 0");
-  if (sweeps < 1) return fail(MACE_E_ARG, "sweeps must be >= 1");
-  const int P = default_rows_per_agent(s);
-  Schedule* sch = get_schedule(s, agent, P);
-  Schedule* full = get_schedule(s, -1, P);
-  if (!sch || !full) return fail(MACE_E_HIP, "schedule upload failed");
-  rc = ensure_workspace(s, 1, std::max(sch->R, full->R));
-  if (rc) return rc;
-  const size_t m = (size_t)s->n_views * s->n_ch;
-  const int64_t nrow = (int64_t)s->N * s->estride;
-  DevBuf<float> dy, dl, dv;
-  HIP_OK(dy.upload(y, m));
-  HIP_OK(dl.upload(lam, m));
-  HIP_OK(dv.upload(v, s->n));
-  hipStream_t st = nullptr;
-  HIP_OK(launch_gather_rows(s->e.p, dy.p, s->row_src.p, nrow, st));
-  HIP_OK(launch_gather_rows(s->lam.p, dl.p, s->row_src.p, nrow, st));
-  // every agent's image = x_init, w_agent = wbar = v so that 2 wbar - w = v
-  std::vector<float> xi((size_t)s->N * s->n);
-  for (int a = 0; a < s->N; ++a) memcpy(xi.data() + (size_t)a * s->n, x_init, sizeof(float) * s->n);
-  HIP_OK(hipMemcpy(s->X.p, xi.data(), sizeof(float) * xi.size(), hipMemcpyHostToDevice));
-  HIP_OK(hipMemcpy(s->wbar.p, dv.p, sizeof(float) * s->n, hipMemcpyDeviceToDevice));
-  HIP_OK(hipMemcpy(s->w.p + (size_t)agent * s->n, dv.p, sizeof(float) * s->n, hipMemcpyDeviceToDevice));
-  const bool fp16 = s->precision == 1;
-  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
-  SvArgs a;
-  fill_args(s, a, pr, 0.5, sigma, fp16);
-  a.R = sch->R;
-  a.strict = P == 1 ? 1 : 0;
-  for (int c = 0; c < 4; ++c) {
-    a.tasks = sch->tasks[c].p;
-    a.T = sch->T[c];
-    HIP_OK(launch_sv(a, kTheta2, s->slots, sch->grid, lds, st));
-    HIP_OK(launch_sv(a, kRefresh, s->slots, sch->grid, lds, st));
-  }
-  a.mann = 0;
-  for (int sw = 0; sw < sweeps; ++sw)
-    for (int c = 0; c < 4; ++c) {
-      a.tasks = sch->tasks[c].p;
-      a.T = sch->T[c];
-      a.part = s->part.p;
-      HIP_OK(launch_sv(a, kSweep, s->slots, sch->grid, lds, st));
-    }
-  HIP_OK(hipMemcpy(x_out, s->X.p + (size_t)agent * s->n, sizeof(float) * s->n, hipMemcpyDeviceToHost));
-  return MACE_OK;
-}

@@ -23,6 +23,26 @@ struct BandEnt {
 
 enum KernelMode { kSweep = 0, kTheta2 = 1, kRefresh = 2 };
 
+// Tasks: slot << kSlotShift | (agent * n_sv + sv); -1 = none.
+constexpr int kSlotShift = 24;
+constexpr int kMaxScanSlots = 128;  // scans per batch (slot field of a task)
+
+// Per-scan state of one slot of a batch (device table entry).
+struct SlotDesc {
+  float* e;           // error sinogram y - A X_i, agent blocks
+  const float* lam;   // inverse-variance weights, agent blocks
+  float* X;           // [N][n] agent states
+  float* w;           // [N][n] Mann state
+  float* wbar;        // [n] mean of w (updated by the epilogue)
+  float* th2;         // [N][n] theta2 = sum_r A_rs^2 Lambda_r
+  double* part;       // [N * n_sv][4] FP64 residual partials per task
+  double* resid;      // [resid_cap] residual trace
+  double* last;       // latest residual (one double)
+  int* counter;       // Mann iterations done
+  int resid_cap;
+  int active;         // 0: the slot's tasks and epilogue are skipped
+};
+
 struct SvArgs {
   int nx, ny, n;        // image
   int S, gx, n_sv;      // super-voxel side, grid width, count
@@ -39,13 +59,7 @@ struct SvArgs {
   const BandEnt* band;  // [(agent * n_sv + sv) * kpad + view]
   const int* band_rows; // [agent * n_sv + sv] rows B of the band (dummy rows at B, B+1)
   int64_t estride;      // per-agent stride of e / lam blocks
-  float* e;             // error sinogram y - A X, agent blocks
-  const float* lam;     // inverse-variance weights, agent blocks
-  float* X;             // [N][n] agent states
-  float* w;             // [N][n] Mann state
-  const float* wbar;    // [n] mean of w at the start of the iteration
-  float* th2;           // [N][n] theta2 = sum_r A_rs^2 Lambda_r
-  double* part;         // [R][4] residual partials of this launch
+  const SlotDesc* slots; // per-scan state, indexed by the task's slot
   int kind;             // 0 quadratic, 1 q-GGMRF (p = 2)
   float invN, is2, rho;
   float relax;          // scale of each coordinate step (1 = exact minimiser)
@@ -68,8 +82,7 @@ hipError_t launch_sv_s8f16(const SvArgs& a, int mode, int slots, int grid, size_
 // Launchers (defined in mace_kernels.hip).
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
 size_t sv_lds_bytes(int bmax, int S, int kpad);
-hipError_t launch_epilogue(const float* w, float* wbar, int N, int n, const double* part,
-                           int nparts, double* resid, int* counter, int max_iters,
+hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int nparts,
                            hipStream_t st);
 hipError_t launch_gather_rows(float* dst, const float* src, const int* row_src, int64_t count,
                               hipStream_t st);

@@ -21,26 +21,26 @@ hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds,
 
 // ---------------- consensus / residual epilogue ----------------
 
-// wbar[s] = mean_i w[i][s]; block 0 also reduces the residual partials in a
-// fixed order and stores r_k = sqrt(num) / sqrt(den > 0 ? den : ||X||^2).
-__global__ __launch_bounds__(256) void epilogue_kernel(const float* __restrict__ w,
-                                                       float* __restrict__ wbar, int N, int n,
-                                                       const double* __restrict__ part,
-                                                       int nparts, double* resid,
-                                                       int* counter, int max_iters) {
+// For every active slot (blockIdx.y): wbar[s] = mean_i w[i][s]; block x = 0
+// also sums the slot's per-task residual partials in a fixed order and stores
+// r_k = sqrt(num) / sqrt(den > 0 ? den : ||X||^2) at the slot's iteration k.
+__global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restrict__ slots, int N,
+                                                       int n, int nparts) {
+  const SlotDesc d = slots[blockIdx.y];
+  if (!d.active) return;
   const int tid = threadIdx.x;
   for (int s = blockIdx.x * blockDim.x + tid; s < n; s += gridDim.x * blockDim.x) {
     float m = 0.0f;
-    for (int i = 0; i < N; ++i) m += w[(size_t)i * n + s];
-    wbar[s] = m / (float)N;
+    for (int i = 0; i < N; ++i) m += d.w[(size_t)i * n + s];
+    d.wbar[s] = m / (float)N;
   }
   if (blockIdx.x == 0) {
     __shared__ double red[3][256];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int p = tid; p < nparts; p += 256) {
-      s0 += part[(size_t)p * 4 + 0];
-      s1 += part[(size_t)p * 4 + 1];
-      s2 += part[(size_t)p * 4 + 2];
+      s0 += d.part[(size_t)p * 4 + 0];
+      s1 += d.part[(size_t)p * 4 + 1];
+      s2 += d.part[(size_t)p * 4 + 2];
     }
     red[0][tid] = s0;
     red[1][tid] = s1;
@@ -55,22 +55,22 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const float* __restrict__
       __syncthreads();
     }
     if (tid == 0) {
-      const int k = *counter;
+      const int k = *d.counter;
       const double den = red[1][0] > 0.0 ? red[1][0] : red[2][0];
       const double r = den > 0.0 ? sqrt(red[0][0]) / sqrt(den) : 0.0;
-      if (k < max_iters) resid[k] = r;
-      *counter = k + 1;
+      if (k < d.resid_cap) d.resid[k] = r;
+      *d.last = r;
+      *d.counter = k + 1;
     }
   }
 }
 
-hipError_t launch_epilogue(const float* w, float* wbar, int N, int n, const double* part,
-                           int nparts, double* resid, int* counter, int max_iters,
+hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int nparts,
                            hipStream_t st) {
-  int grid = (n + 255) / 256;
-  if (grid > 2048) grid = 2048;
-  hipLaunchKernelGGL(epilogue_kernel, dim3(grid), dim3(256), 0, st, w, wbar, N, n, part, nparts,
-                     resid, counter, max_iters);
+  if (n_slots <= 0) return hipSuccess;
+  int gx = (n + 255) / 256;
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(epilogue_kernel, dim3(gx, n_slots), dim3(256), 0, st, slots, N, n, nparts);
   return hipGetLastError();
 }
 

@@ -1,0 +1,131 @@
+// Host-side runtime types shared by the library's translation units.
+#pragma once
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mace.h"
+#include "mace_internal.h"
+
+namespace mace {
+
+// Records the calling thread's error message and returns code.
+int fail(int code, const char* fmt, ...);
+const std::string& last_error_text();
+
+#define HIP_OK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t _e = (expr);                                                                \
+    if (_e != hipSuccess)                                                                  \
+      return ::mace::fail(_e == hipErrorOutOfMemory ? MACE_E_NOMEM : MACE_E_HIP,           \
+                          "%s: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, __LINE__); \
+  } while (0)
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t count = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    count = 0;
+  }
+  hipError_t alloc(size_t n) {
+    reset();
+    count = n;
+    if (n == 0) return hipSuccess;
+    return hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
+  }
+  hipError_t upload(const T* h, size_t n) {
+    hipError_t e = alloc(n);
+    if (e != hipSuccess || n == 0) return e;
+    return hipMemcpy(p, h, n * sizeof(T), hipMemcpyHostToDevice);
+  }
+  size_t bytes() const { return count * sizeof(T); }
+};
+
+// Task tables of one schedule: one [R][T] table per colour phase.
+struct Schedule {
+  DevBuf<int> tasks[4];
+  int R = 0, T[4] = {0, 0, 0, 0}, grid = 0;
+};
+
+// Device state of one scan.
+struct ScanSlot {
+  DevBuf<float> e, lam, yb, X, w, wbar, th2;
+  DevBuf<double> part, resid;
+  DevBuf<int> counter;
+  int resid_cap = 0;
+  int64_t bytes() const {
+    return (int64_t)(e.bytes() + lam.bytes() + yb.bytes() + X.bytes() + w.bytes() + wbar.bytes() +
+                     th2.bytes() + part.bytes() + resid.bytes() + counter.bytes());
+  }
+};
+
+// Iteration graph: the launches of one Mann iteration, captured once.
+struct IterGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~IterGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+}  // namespace mace
+
+struct mace_system {
+  int nx = 0, ny = 0, n = 0, n_views = 0, n_ch = 0, N = 0;
+  int Kmax = 0, slots = 0, kpad = 0;
+  int S = 0, gx = 0, gy = 0, n_sv = 0;
+  int bmax = 0;
+  int wmax = 0;
+  int precision = 0;
+  int rows_per_agent = 0;
+  int fp32_tail = 0;
+  int refresh_every = 0;
+  int64_t estride = 0;
+  std::vector<int> view_agent;          // [n_views]
+  std::vector<std::vector<int>> views;  // agent -> its views, ascending
+  std::vector<int> sv_pix0;             // [n_sv + 1]
+  std::vector<int> colour_svs[4];       // SVs of each colour in schedule order
+  // device copies of the matrix
+  mace::DevBuf<float2> aval;
+  mace::DevBuf<__half2> hval;
+  mace::DevBuf<float> hscale;
+  mace::DevBuf<uint16_t> aoff;
+  mace::DevBuf<mace::BandEnt> band;
+  mace::DevBuf<int> band_rows;
+  mace::DevBuf<int> d_sv_pix0;
+  mace::DevBuf<int> row_src;  // agent-block row -> global row (or -1)
+  std::map<std::tuple<int, int, int>, std::unique_ptr<mace::Schedule>> schedules;
+  // scan slots: slot 0 serves mace_solve / mace_prox; batches use 0..B-1
+  std::vector<std::unique_ptr<mace::ScanSlot>> scan;
+  mace::DevBuf<mace::SlotDesc> table;  // device slot table
+  std::vector<mace::SlotDesc> htable;
+  mace::DevBuf<double> lastres;
+  hipStream_t stream = nullptr;
+  std::map<std::tuple<int, int, int, int, uint64_t>, std::unique_ptr<mace::IterGraph>> graphs;
+  int64_t matrix_bytes = 0;
+  bool timing = false;
+  double relax = 0.0;  // 0: automatic (1 for the sequential schedule, 0.5 otherwise)
+  std::vector<hipEvent_t> ev;
+  ~mace_system();
+};
+
+namespace mace {
+int default_rows_per_agent(const mace_system* s);
+Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P);
+int check_prior(const mace_prior* pr);
+void fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, double rho, double sigma,
+               bool fp16);
+}  // namespace mace

@@ -1,0 +1,485 @@
+// Host runtime of the MACE library, part 2: scan slots, the Mann-iteration
+// driver (Algorithm 1) for one scan or a batch of scans of one geometry, the
+// single-agent partial prox, and state read-back.
+//
+// All launches of a solve run on the system's private stream.  One Mann
+// iteration (4 colour-phase sweep launches per ICD pass, then the consensus /
+// residual epilogue) is captured once in a hipGraph and replayed; the slot
+// table lives in device memory, so a slot that has converged is switched off
+// without re-capturing.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <tuple>
+
+#include "mace_runtime.h"
+
+using namespace mace;
+
+namespace {
+
+int ensure_slot(mace_system* s, int idx, int max_iters) {
+  while ((int)s->scan.size() <= idx) s->scan.push_back(std::make_unique<ScanSlot>());
+  ScanSlot& q = *s->scan[idx];
+  const size_t nimg = (size_t)s->N * s->n;
+  const size_t nrow = (size_t)s->N * s->estride;
+  if (q.e.count != nrow) {
+    HIP_OK(q.e.alloc(nrow));
+    HIP_OK(q.lam.alloc(nrow));
+    HIP_OK(q.yb.alloc(nrow));
+    HIP_OK(q.X.alloc(nimg));
+    HIP_OK(q.w.alloc(nimg));
+    HIP_OK(q.th2.alloc(nimg));
+    HIP_OK(q.wbar.alloc(s->n));
+    HIP_OK(q.part.alloc((size_t)s->N * s->n_sv * 4));
+    HIP_OK(q.counter.alloc(1));
+  }
+  const int cap = std::max(1, max_iters);
+  if (q.resid_cap < cap) {
+    HIP_OK(q.resid.alloc((size_t)cap));
+    q.resid_cap = cap;
+  }
+  return MACE_OK;
+}
+
+// Device slot table for slots [0, n) with the given active flags.
+int upload_table(mace_system* s, int n, const std::vector<int>& active, hipStream_t st) {
+  // allocated once at the maximum size: captured graphs hold these addresses
+  if (s->lastres.count < (size_t)kMaxScanSlots) HIP_OK(s->lastres.alloc(kMaxScanSlots));
+  if (s->table.count < (size_t)kMaxScanSlots) HIP_OK(s->table.alloc(kMaxScanSlots));
+  if (n > kMaxScanSlots) return fail(MACE_E_ARG, "too many scan slots");
+  s->htable.assign(n, SlotDesc{});
+  for (int i = 0; i < n; ++i) {
+    ScanSlot& q = *s->scan[i];
+    SlotDesc& d = s->htable[i];
+    d.e = q.e.p;
+    d.lam = q.lam.p;
+    d.X = q.X.p;
+    d.w = q.w.p;
+    d.wbar = q.wbar.p;
+    d.th2 = q.th2.p;
+    d.part = q.part.p;
+    d.resid = q.resid.p;
+    d.last = s->lastres.p + i;
+    d.counter = q.counter.p;
+    d.resid_cap = q.resid_cap;
+    d.active = active[i];
+  }
+  HIP_OK(hipMemcpyAsync(s->table.p, s->htable.data(), sizeof(SlotDesc) * n, hipMemcpyHostToDevice, st));
+  return MACE_OK;
+}
+
+int set_active(mace_system* s, int i, int on, hipStream_t st) {
+  s->htable[i].active = on;
+  HIP_OK(hipMemcpyAsync(&s->table.p[i].active, &s->htable[i].active, sizeof(int),
+                        hipMemcpyHostToDevice, st));
+  return MACE_OK;
+}
+
+// Sweep-mode launches over all four colour phases (mode kTheta2 / kRefresh
+// for set-up), with the slot table seen from `slot_base`.
+int launch_phases(mace_system* s, const Schedule* sch, SvArgs a, int mode, hipStream_t st,
+                  const SlotDesc* slot_base) {
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
+  a.R = sch->R;
+  a.slots = slot_base;
+  for (int c = 0; c < 4; ++c) {
+    a.tasks = sch->tasks[c].p;
+    a.T = sch->T[c];
+    HIP_OK(launch_sv(a, mode, s->slots, sch->grid, lds, st));
+  }
+  return MACE_OK;
+}
+
+// Load y / Lambda (device, global row order) of slot i and set its initial
+// state: w = w_init (or 0), X = G(w), e = y - A X, theta2; residual counter 0.
+int start_slot(mace_system* s, int i, const float* y, const float* lam, const float* w_init,
+               const SvArgs& base, hipStream_t st) {
+  ScanSlot& q = *s->scan[i];
+  const int64_t nrow = (int64_t)s->N * s->estride;
+  HIP_OK(launch_gather_rows(q.yb.p, y, s->row_src.p, nrow, st));
+  HIP_OK(launch_copy(q.e.p, q.yb.p, nrow, st));
+  HIP_OK(launch_gather_rows(q.lam.p, lam, s->row_src.p, nrow, st));
+  const int64_t nimg = (int64_t)s->N * s->n;
+  if (w_init)
+    HIP_OK(launch_copy(q.w.p, w_init, nimg, st));
+  else
+    HIP_OK(launch_fill(q.w.p, 0.f, nimg, st));
+  HIP_OK(launch_broadcast_mean(q.w.p, q.wbar.p, q.X.p, s->N, s->n, st));
+  HIP_OK(hipMemsetAsync(q.counter.p, 0, sizeof(int), st));
+  // theta2 (and e = y - A X when X != 0) through a one-slot schedule that
+  // sees the table from this slot on
+  const int P = default_rows_per_agent(s);
+  Schedule* one = get_schedule(s, 1, -1, P);
+  if (!one) return fail(MACE_E_HIP, "schedule upload failed");
+  SvArgs a = base;
+  a.strict = P == 1 ? 1 : 0;
+  int rc = launch_phases(s, one, a, kTheta2, st, s->table.p + i);
+  if (rc) return rc;
+  if (w_init) {
+    rc = launch_phases(s, one, a, kRefresh, st, s->table.p + i);
+    if (rc) return rc;
+  }
+  return MACE_OK;
+}
+
+// e = y - A X for every active slot of the batch (FP32 drift), and theta2 too
+// when the matrix values change precision.
+int refresh_batch(mace_system* s, int n_slots, const Schedule* sch, const SvArgs& base,
+                  bool theta2, hipStream_t st) {
+  for (int i = 0; i < n_slots; ++i) {
+    if (!s->htable[i].active) continue;
+    ScanSlot& q = *s->scan[i];
+    HIP_OK(launch_copy(q.e.p, q.yb.p, (int64_t)s->N * s->estride, st));
+  }
+  if (theta2) {
+    int rc = launch_phases(s, sch, base, kTheta2, st, s->table.p);
+    if (rc) return rc;
+  }
+  return launch_phases(s, sch, base, kRefresh, st, s->table.p);
+}
+
+// The launches of one Mann iteration: `sweeps` ICD passes (the last one with
+// the reflection + Mann update) and the epilogue.
+int enqueue_iteration(mace_system* s, const Schedule* sch, int n_slots, SvArgs a, int sweeps,
+                      hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
+  a.R = sch->R;
+  a.slots = s->table.p;
+  if (ev0) HIP_OK(hipEventRecord(ev0, st));
+  for (int sw = 0; sw < sweeps; ++sw) {
+    a.mann = (sw == sweeps - 1) ? 1 : 0;
+    for (int c = 0; c < 4; ++c) {
+      a.tasks = sch->tasks[c].p;
+      a.T = sch->T[c];
+      HIP_OK(launch_sv(a, kSweep, s->slots, sch->grid, lds, st));
+    }
+  }
+  if (ev1) HIP_OK(hipEventRecord(ev1, st));
+  HIP_OK(launch_epilogue(s->table.p, n_slots, s->N, s->n, s->N * s->n_sv, st));
+  return MACE_OK;
+}
+
+uint64_t args_key(const SvArgs& a) {
+  uint64_t h = 1469598103934665603ULL;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ULL;
+  };
+  mix(&a.kind, sizeof a.kind);
+  mix(&a.invN, sizeof(float) * 4);  // invN, is2, rho, relax
+  mix(&a.bedge, sizeof(float) * 6);
+  mix(&a.fp16, sizeof a.fp16);
+  mix(&a.strict, sizeof a.strict);
+  return h;
+}
+
+// One Mann iteration through a captured graph.  The first iteration with a
+// given configuration runs eagerly (it also performs the one-time kernel
+// attribute set-up, which stays out of the capture); the second captures.
+int run_iteration_graph(mace_system* s, const Schedule* sch, int n_slots, const SvArgs& a,
+                        int sweeps, int P, hipStream_t st) {
+  const auto key = std::make_tuple(n_slots, P, sweeps, s->precision, args_key(a));
+  auto it = s->graphs.find(key);
+  IterGraph* g = nullptr;
+  if (it == s->graphs.end()) {
+    s->graphs[key] = nullptr;
+    return enqueue_iteration(s, sch, n_slots, a, sweeps, st, nullptr, nullptr);
+  }
+  if (!it->second) {
+    auto ng = std::make_unique<IterGraph>();
+    HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_iteration(s, sch, n_slots, a, sweeps, st, nullptr, nullptr);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    HIP_OK(e);
+    ng->graph = graph;
+    HIP_OK(hipGraphInstantiate(&ng->exec, graph, nullptr, nullptr, 0));
+    g = ng.get();
+    s->graphs[key] = std::move(ng);
+  } else {
+    g = it->second.get();
+  }
+  HIP_OK(hipGraphLaunch(g->exec, st));
+  return MACE_OK;
+}
+
+struct BatchIO {
+  const float* y;
+  const float* lam;
+  const float* w_init;
+  float* x_out;
+  mace_info* info;
+};
+
+// Partial-update MACE (Algorithm 1) for `n` scans of this geometry at once.
+// Each scan stops on its own residual; finished scans are switched off in the
+// slot table while the others continue.
+int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior* pr, double rho,
+                     double sigma, int sweeps, int max_iters, double tol, hipStream_t user) {
+  int rc = check_prior(pr);
+  if (rc) return rc;
+  if (n < 1 || n > kMaxScanSlots) return fail(MACE_E_ARG, "batch size must be in [1, %d]", kMaxScanSlots);
+  if (!(rho > 0 && rho < 1)) return fail(MACE_E_ARG, "rho must be in (0, 1)");
+  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(MACE_E_ARG, "sigma must be > 0");
+  if (sweeps < 1) return fail(MACE_E_ARG, "sweeps must be >= 1");
+  if (max_iters < 0) return fail(MACE_E_ARG, "max_iters must be >= 0");
+  for (int i = 0; i < n; ++i)
+    if (!io[i].y || !io[i].lam || !io[i].x_out) return fail(MACE_E_ARG, "NULL scan argument");
+  hipStream_t st = s->stream;
+  if (user) HIP_OK(hipStreamSynchronize(user));  // the caller's inputs are ready
+  // concurrency per (scan, agent): keep about the same number of rows in total
+  int P = default_rows_per_agent(s);
+  if (n > 1 && s->rows_per_agent == 0) P = std::max(1, P / n);
+  Schedule* sch = get_schedule(s, n, -1, P);
+  if (!sch) return fail(MACE_E_HIP, "schedule upload failed");
+  for (int i = 0; i < n; ++i) {
+    rc = ensure_slot(s, i, max_iters);
+    if (rc) return rc;
+  }
+  std::vector<int> active(n, 1);
+  rc = upload_table(s, n, active, st);
+  if (rc) return rc;
+  const bool fp16 = s->precision == 1;
+  SvArgs a;
+  fill_args(s, a, pr, rho, sigma, fp16);
+  a.strict = P == 1 ? 1 : 0;
+  if (s->relax <= 0.0) a.relax = P == 1 ? 1.0f : 0.5f;
+  for (int i = 0; i < n; ++i) {
+    rc = start_slot(s, i, io[i].y, io[i].lam, io[i].w_init, a, st);
+    if (rc) return rc;
+  }
+  HIP_OK(hipMemsetAsync(s->lastres.p, 0, sizeof(double) * n, st));
+  const bool timing = s->timing;
+  if (timing && (int)s->ev.size() < 2 * max_iters + 2) {
+    for (auto e : s->ev) (void)hipEventDestroy(e);
+    s->ev.assign(2 * max_iters + 2, nullptr);
+    for (auto& e : s->ev) HIP_OK(hipEventCreate(&e));
+  }
+  if (timing) HIP_OK(hipEventRecord(s->ev[2 * max_iters], st));
+  std::vector<int> iters(n, 0), status(n, MACE_OK);
+  std::vector<double> last(n, 0.0);
+  int live = n, it = 0;
+  bool tail_done = false;
+  for (; it < max_iters && live > 0; ++it) {
+    const bool tail = fp16 && s->fp32_tail > 0 && it >= max_iters - s->fp32_tail;
+    if (tail && !tail_done) {
+      // switch to FP32 values: rebuild e = y - A X and theta2 with them
+      a.fp16 = 0;
+      tail_done = true;
+      rc = refresh_batch(s, n, sch, a, true, st);
+      if (rc) return rc;
+    } else if (s->refresh_every > 0 && it > 0 && it % s->refresh_every == 0) {
+      rc = refresh_batch(s, n, sch, a, false, st);
+      if (rc) return rc;
+    }
+    if (timing)
+      rc = enqueue_iteration(s, sch, n, a, sweeps, st, s->ev[2 * it], s->ev[2 * it + 1]);
+    else
+      rc = run_iteration_graph(s, sch, n, a, sweeps, P, st);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i)
+      if (s->htable[i].active) iters[i] = it + 1;
+    if (tol > 0) {
+      HIP_OK(hipMemcpyAsync(last.data(), s->lastres.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      for (int i = 0; i < n; ++i) {
+        if (!s->htable[i].active) continue;
+        const bool bad = !std::isfinite(last[i]);
+        if (bad || last[i] < tol) {
+          if (bad) status[i] = MACE_E_NONFINITE;
+          rc = set_active(s, i, 0, st);
+          if (rc) return rc;
+          --live;
+        }
+      }
+    }
+  }
+  if (timing) HIP_OK(hipEventRecord(s->ev[2 * max_iters + 1], st));
+  HIP_OK(hipMemcpyAsync(last.data(), s->lastres.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  double sweep_ms = 0.0, iter_ms = 0.0;
+  if (timing) {
+    for (int k = 0; k < it; ++k) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]));
+      sweep_ms += ms;
+    }
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, s->ev[2 * max_iters], s->ev[2 * max_iters + 1]));
+    iter_ms = ms;
+  }
+  int worst = MACE_OK;
+  for (int i = 0; i < n; ++i) {
+    ScanSlot& q = *s->scan[i];
+    if (max_iters == 0) HIP_OK(launch_broadcast_mean(q.w.p, q.wbar.p, q.X.p, s->N, s->n, st));
+    // x = mean_i w_i: wbar holds it after the scan's last epilogue
+    HIP_OK(hipMemcpyAsync(io[i].x_out, q.wbar.p, sizeof(float) * s->n, hipMemcpyDeviceToDevice, st));
+    if (status[i] == MACE_OK && !std::isfinite(last[i])) status[i] = MACE_E_NONFINITE;
+    if (status[i] == MACE_OK && tol > 0 && !(last[i] < tol)) status[i] = MACE_W_MAXITER;
+    if (io[i].info) {
+      io[i].info->iters = iters[i];
+      io[i].info->residual = last[i];
+      io[i].info->equits = (double)sweeps * iters[i];
+      io[i].info->status = status[i];
+      io[i].info->sweep_ms = sweep_ms;
+      io[i].info->sweep_launches = timing ? it * sweeps * 4 : 0;
+      io[i].info->iter_ms = iter_ms;
+    }
+    if (status[i] == MACE_E_NONFINITE) worst = MACE_E_NONFINITE;
+    else if (status[i] == MACE_W_MAXITER && worst == MACE_OK) worst = MACE_W_MAXITER;
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  if (worst == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "non-finite residual");
+  return worst;
+}
+
+}  // namespace
+
+extern "C" int mace_solve_dev(mace_system* s, const float* y, const float* lam,
+                              const mace_prior* pr, double rho, double sigma, int32_t sweeps,
+                              int32_t max_iters, double tol, const float* w_init, float* x_out,
+                              mace_info* info, void* stream) {
+  if (!s || !y || !lam || !x_out) return fail(MACE_E_ARG, "NULL argument");
+  BatchIO io{y, lam, w_init, x_out, info};
+  return solve_batch_impl(s, 1, &io, pr, rho, sigma, sweeps, max_iters, tol, (hipStream_t)stream);
+}
+
+extern "C" int mace_solve_batch_dev(mace_system* s, int32_t n_scans, const float* const* y,
+                                    const float* const* lam, const mace_prior* pr, double rho,
+                                    double sigma, int32_t sweeps, int32_t max_iters, double tol,
+                                    float* const* x_out, mace_info* info, void* stream) {
+  if (!s || !y || !lam || !x_out) return fail(MACE_E_ARG, "NULL argument");
+  if (n_scans < 1 || n_scans > kMaxScanSlots) return fail(MACE_E_ARG, "n_scans must be in [1, %d]", kMaxScanSlots);
+  std::vector<BatchIO> io(n_scans);
+  for (int i = 0; i < n_scans; ++i) io[i] = BatchIO{y[i], lam[i], nullptr, x_out[i], info ? info + i : nullptr};
+  return solve_batch_impl(s, n_scans, io.data(), pr, rho, sigma, sweeps, max_iters, tol,
+                          (hipStream_t)stream);
+}
+
+extern "C" int mace_solve_batch(mace_system* s, int32_t n_scans, const float* const* y,
+                                const float* const* lam, const mace_prior* pr, double rho,
+                                double sigma, int32_t sweeps, int32_t max_iters, double tol,
+                                float* const* x_out, mace_info* info) {
+  if (!s || !y || !lam || !x_out) return fail(MACE_E_ARG, "NULL argument");
+  if (n_scans < 1 || n_scans > kMaxScanSlots) return fail(MACE_E_ARG, "n_scans must be in [1, %d]", kMaxScanSlots);
+  const size_t m = (size_t)s->n_views * s->n_ch;
+  std::vector<std::unique_ptr<DevBuf<float>>> bufs;
+  std::vector<BatchIO> io(n_scans);
+  for (int i = 0; i < n_scans; ++i) {
+    if (!y[i] || !lam[i] || !x_out[i]) return fail(MACE_E_ARG, "NULL scan argument");
+    auto dy = std::make_unique<DevBuf<float>>(), dl = std::make_unique<DevBuf<float>>(),
+         dx = std::make_unique<DevBuf<float>>();
+    HIP_OK(dy->upload(y[i], m));
+    HIP_OK(dl->upload(lam[i], m));
+    HIP_OK(dx->alloc(s->n));
+    io[i] = BatchIO{dy->p, dl->p, nullptr, dx->p, info ? info + i : nullptr};
+    bufs.push_back(std::move(dy));
+    bufs.push_back(std::move(dl));
+    bufs.push_back(std::move(dx));
+  }
+  int rc = solve_batch_impl(s, n_scans, io.data(), pr, rho, sigma, sweeps, max_iters, tol, nullptr);
+  if (rc < 0 && rc != MACE_E_NONFINITE) return rc;
+  const std::string saved = last_error_text();
+  for (int i = 0; i < n_scans; ++i)
+    HIP_OK(hipMemcpy(x_out[i], io[i].x_out, sizeof(float) * s->n, hipMemcpyDeviceToHost));
+  if (rc == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "%s", saved.c_str());
+  return rc;
+}
+
+extern "C" int mace_solve(mace_system* s, const float* y, const float* lam, const mace_prior* pr,
+                          double rho, double sigma, int32_t sweeps, int32_t max_iters, double tol,
+                          const float* w_init, float* x_out, mace_info* info) {
+  if (!s || !y || !lam || !x_out) return fail(MACE_E_ARG, "NULL argument");
+  const size_t m = (size_t)s->n_views * s->n_ch, nimg = (size_t)s->N * s->n;
+  DevBuf<float> dy, dl, dw, dx;
+  HIP_OK(dy.upload(y, m));
+  HIP_OK(dl.upload(lam, m));
+  if (w_init) HIP_OK(dw.upload(w_init, nimg));
+  HIP_OK(dx.alloc(s->n));
+  BatchIO io{dy.p, dl.p, w_init ? dw.p : nullptr, dx.p, info};
+  int rc = solve_batch_impl(s, 1, &io, pr, rho, sigma, sweeps, max_iters, tol, nullptr);
+  if (rc < 0 && rc != MACE_E_NONFINITE) return rc;
+  const std::string saved = last_error_text();
+  HIP_OK(hipMemcpy(x_out, dx.p, sizeof(float) * s->n, hipMemcpyDeviceToHost));
+  if (rc == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "%s", saved.c_str());
+  return rc;
+}
+
+extern "C" int mace_prox(mace_system* s, int32_t agent, const float* y, const float* lam,
+                         const mace_prior* pr, double sigma, const float* v,
+                         const float* x_init, int32_t sweeps, float* x_out) {
+  if (!s || !y || !lam || !v || !x_init || !x_out) return fail(MACE_E_ARG, "NULL argument");
+  if (agent < 0 || agent >= s->N) return fail(MACE_E_ARG, "agent %d out of range", agent);
+  int rc = check_prior(pr);
+  if (rc) return rc;
+  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(MACE_E_ARG, "sigma must be > 0");
+  if (sweeps < 1) return fail(MACE_E_ARG, "sweeps must be >= 1");
+  const int P = default_rows_per_agent(s);
+  Schedule* sch = get_schedule(s, 1, agent, P);
+  if (!sch) return fail(MACE_E_HIP, "schedule upload failed");
+  rc = ensure_slot(s, 0, 1);
+  if (rc) return rc;
+  hipStream_t st = s->stream;
+  rc = upload_table(s, 1, std::vector<int>{1}, st);
+  if (rc) return rc;
+  ScanSlot& q = *s->scan[0];
+  const size_t m = (size_t)s->n_views * s->n_ch;
+  const int64_t nrow = (int64_t)s->N * s->estride;
+  DevBuf<float> dy, dl, dv;
+  HIP_OK(dy.upload(y, m));
+  HIP_OK(dl.upload(lam, m));
+  HIP_OK(dv.upload(v, s->n));
+  HIP_OK(launch_gather_rows(q.yb.p, dy.p, s->row_src.p, nrow, st));
+  HIP_OK(launch_copy(q.e.p, q.yb.p, nrow, st));
+  HIP_OK(launch_gather_rows(q.lam.p, dl.p, s->row_src.p, nrow, st));
+  // the agent's image = x_init, its w = wbar = v, so that 2 wbar - w = v
+  HIP_OK(hipMemcpyAsync(q.X.p + (size_t)agent * s->n, x_init, sizeof(float) * s->n,
+                        hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(q.wbar.p, dv.p, sizeof(float) * s->n, hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipMemcpyAsync(q.w.p + (size_t)agent * s->n, dv.p, sizeof(float) * s->n,
+                        hipMemcpyDeviceToDevice, st));
+  const bool fp16 = s->precision == 1;
+  SvArgs a;
+  fill_args(s, a, pr, 0.5, sigma, fp16);
+  a.strict = P == 1 ? 1 : 0;
+  rc = launch_phases(s, sch, a, kTheta2, st, s->table.p);
+  if (rc) return rc;
+  rc = launch_phases(s, sch, a, kRefresh, st, s->table.p);
+  if (rc) return rc;
+  a.mann = 0;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    rc = launch_phases(s, sch, a, kSweep, st, s->table.p);
+    if (rc) return rc;
+  }
+  HIP_OK(hipMemcpyAsync(x_out, q.X.p + (size_t)agent * s->n, sizeof(float) * s->n,
+                        hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return MACE_OK;
+}
+
+extern "C" int mace_get_state(const mace_system* s, float* w, float* X) {
+  if (!s) return fail(MACE_E_ARG, "NULL system");
+  if (s->scan.empty() || !s->scan[0]->w.p) return fail(MACE_E_ARG, "no solve has run on this system");
+  const size_t bytes = (size_t)s->N * s->n * sizeof(float);
+  if (w) HIP_OK(hipMemcpy(w, s->scan[0]->w.p, bytes, hipMemcpyDeviceToHost));
+  if (X) HIP_OK(hipMemcpy(X, s->scan[0]->X.p, bytes, hipMemcpyDeviceToHost));
+  return MACE_OK;
+}
+
+extern "C" int mace_get_error_sinogram(const mace_system* s, float* e) {
+  if (!s || !e) return fail(MACE_E_ARG, "NULL argument");
+  if (s->scan.empty() || !s->scan[0]->e.p) return fail(MACE_E_ARG, "no solve has run on this system");
+  const ScanSlot& q = *s->scan[0];
+  std::vector<float> blk(q.e.count);
+  HIP_OK(hipMemcpy(blk.data(), q.e.p, q.e.bytes(), hipMemcpyDeviceToHost));
+  for (int a = 0; a < s->N; ++a)
+    for (size_t kl = 0; kl < s->views[a].size(); ++kl)
+      memcpy(e + (size_t)s->views[a][kl] * s->n_ch, blk.data() + (size_t)a * s->estride + kl * s->n_ch,
+             sizeof(float) * s->n_ch);
+  return MACE_OK;
+}

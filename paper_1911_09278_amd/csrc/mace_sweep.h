@@ -123,7 +123,7 @@ __device__ __forceinline__ void load_rec_at(const float2* vb, const __half2* hb,
 __host__ __device__ inline size_t row_lds_bytes(int bmax, int S, int kpad) {
   const size_t HS = S + 2;
   const size_t per_row = (size_t)bmax * 12 + HS * HS * 8 + (size_t)S * S * 8 + (size_t)kpad * 8;
-  const size_t red = kRowLanes * 3 * sizeof(double);  // end-of-kernel reduction
+  const size_t red = kRowLanes * 3 * sizeof(double);  // per-task FP64 reduction
   return per_row > red ? per_row : red;
 }
 
@@ -134,9 +134,14 @@ struct Stage {
   static constexpr int HS = S + 2;
   static constexpr int HC = (HS * HS + kRowLanes - 1) / kRowLanes;  // halo cells per lane
   static constexpr int PPL = (S * S + kRowLanes - 1) / kRowLanes;   // pixels per lane
-  int task;
+  int task;   // agent * n_sv + sv, or -1
   int B;
   int pix0;
+  float* e;   // the task's slot: error sinogram, agent state, Mann state,
+  float* X;   // theta2 and residual partials
+  float* w;
+  float* th2;
+  double* part;
   BandEnt be[SL];
   float ev[SL][WM];
   float lv[SL][WM];
@@ -173,7 +178,6 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
   const int noff = lr < 8 ? ndi * HS + ndj : 0;
   const float proxw = lr == 8 ? a.is2 : 0.0f;  // lane 8 adds the prox term
 
-  double acc_num = 0.0, acc_den = 0.0, acc_x2 = 0.0;
   const bool row_ok = row < a.R;
   // strict: this row sees every earlier task's changes (one SV of an agent
   // at a time); otherwise the next band may be staged before the current
@@ -182,23 +186,43 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
 
   // ---- staging of task t into registers ----
   auto stage_load = [&](int t, St& st) {
-    st.task = (row_ok && t < a.T) ? a.tasks[(size_t)row * a.T + t] : -1;
-    if (st.task < 0) return;
-    const int agent = st.task / a.n_sv;
-    const int sv = st.task - agent * a.n_sv;
+    const int raw = (row_ok && t < a.T) ? a.tasks[(size_t)row * a.T + t] : -1;
+    st.task = -1;
+    if (raw < 0) return;
+    const int local = raw & ((1 << kSlotShift) - 1);
+    const SlotDesc* sd = a.slots + (raw >> kSlotShift);
+    const int agent = local / a.n_sv;
+    const int sv = local - agent * a.n_sv;
     const int sy = sv / a.gx, sx = sv - sy * a.gx;
     const int y0 = sy * S, x0 = sx * S;
     const int sh = min(S, a.ny - y0), sw = min(S, a.nx - x0);
     const size_t agent_sv = (size_t)agent * a.n_sv + sv;
     const BandEnt* be = a.band + agent_sv * a.kpad;
-    const float* eag = a.e + (size_t)agent * a.estride;
-    const float* lag = a.lam + (size_t)agent * a.estride;
     const size_t img = (size_t)agent * a.n;
+    // slot pointers and the task's tables are independent loads
+    float* se = sd->e;
+    const float* slam = sd->lam;
+    float* sX = sd->X;
+    float* sw_ = sd->w;
+    const float* swb = sd->wbar;
+    float* sth2 = sd->th2;
+    double* spart = sd->part;
+    const int sactive = sd->active;
     st.B = a.band_rows[agent_sv];
     st.pix0 = a.sv_pix0[sv];
 #pragma unroll
+    for (int sl = 0; sl < SL; ++sl) st.be[sl] = be[sl * kRowLanes + lr];
+    if (!sactive) return;
+    st.task = local;
+    st.e = se;
+    st.X = sX;
+    st.w = sw_;
+    st.th2 = sth2;
+    st.part = spart;
+    const float* eag = se + (size_t)agent * a.estride;
+    const float* lag = slam + (size_t)agent * a.estride;
+#pragma unroll
     for (int sl = 0; sl < SL; ++sl) {
-      st.be[sl] = be[sl * kRowLanes + lr];
       const int wdt = min((int)st.be[sl].width, WM);
 #pragma unroll
       for (int c = 0; c < WM; ++c) {
@@ -217,7 +241,7 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
         const int hi = c / HS, hj = c - (c / HS) * HS;
         const int iy = y0 - 1 + hi, ix = x0 - 1 + hj;
         const bool in = c < HS * HS && iy >= 0 && iy < a.ny && ix >= 0 && ix < a.nx;
-        st.hv[u] = in ? a.X[img + (size_t)iy * a.nx + ix] : 0.0f;
+        st.hv[u] = in ? sX[img + (size_t)iy * a.nx + ix] : 0.0f;
       }
     }
     if (MODE == kSweep) {
@@ -230,9 +254,9 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
         if (p < sh * sw) {
           const int pi = p / sw, pj = p - (p / sw) * sw;
           const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
-          st.wb[u] = a.wbar[pix];
-          st.wo[u] = a.w[img + pix];
-          st.t2[u] = a.th2[img + pix];
+          st.wb[u] = swb[pix];
+          st.wo[u] = sw_[img + pix];
+          st.t2[u] = sth2[img + pix];
         }
       }
     }
@@ -253,8 +277,11 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
       const size_t agent_sv = (size_t)agent * a.n_sv + sv;
       const BandEnt* be = a.band + agent_sv * a.kpad;
       const int B = st.B;
-      float* eag = a.e + (size_t)agent * a.estride;
-      const float* lag = a.lam + (size_t)agent * a.estride;
+      float* eag = st.e + (size_t)agent * a.estride;
+      float* cX = st.X;
+      float* cw = st.w;
+      float* cth2 = st.th2;
+      double* cpart = st.part;
       const size_t img = (size_t)agent * a.n;
       BandEnt cb[SL];
 
@@ -277,13 +304,6 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
             band[cb[sl].lds_row + c] = make_float2(ev[c], st.lv[sl][c]);
             if (MODE == kSweep) e0[cb[sl].lds_row + c] = ev[c];
           }
-        for (int c = WM; c < wdt; ++c) {  // bands wider than WM (not expected)
-          float e1 = 0.0f, l1 = 0.0f;
-          if (MODE == kSweep) e1 = eag[cb[sl].gstart + c];
-          if (MODE != kRefresh) l1 = lag[cb[sl].gstart + c];
-          band[cb[sl].lds_row + c] = make_float2(e1, l1);
-          if (MODE == kSweep) e0[cb[sl].lds_row + c] = e1;
-        }
       }
       if (lr < 2) band[B + lr] = make_float2(0.0f, 0.0f);
       if (MODE != kTheta2) {
@@ -356,7 +376,7 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
           const float th = row_sum16(part);
           if (lr == 0) {
             const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
-            a.th2[img + pix] = th;
+            cth2[img + pix] = th;
           }
         } else {  // kRefresh: accumulate -A x into the band
           const float xs = halo[cidx].x;
@@ -414,6 +434,7 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
         }
       }
       if (MODE == kSweep) {
+        double pn = 0.0, pd = 0.0, px = 0.0;
 #pragma unroll
         for (int u = 0; u < St::PPL; ++u) {
           const int p = u * kRowLanes + lr;
@@ -421,17 +442,39 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
             const int pi = p / sw, pj = p - (p / sw) * sw;
             const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
             const float xn = halo[(pi + 1) * HS + pj + 1].x;
-            a.X[img + pix] = xn;
+            cX[img + pix] = xn;
             if (a.mann) {
               const float wo = cwo[u], wb = cwb[u];
               const float v = 2.0f * wb - wo;
-              a.w[img + pix] = a.rho * (2.0f * xn - v) + (1.0f - a.rho) * wo;
+              cw[img + pix] = a.rho * (2.0f * xn - v) + (1.0f - a.rho) * wo;
               const double d = (double)xn - (double)wb;
-              acc_num += d * d;
-              acc_den += (double)wo * (double)wo;
-              acc_x2 += (double)xn * (double)xn;
+              pn += d * d;
+              pd += (double)wo * (double)wo;
+              px += (double)xn * (double)xn;
             }
           }
+        }
+        if (a.mann) {
+          // the task's FP64 partials, summed over the row in a fixed order
+          // through LDS (the band is free after the flush)
+          double* red = reinterpret_cast<double*>(base);
+          __builtin_amdgcn_wave_barrier();
+          red[lr * 3 + 0] = pn;
+          red[lr * 3 + 1] = pd;
+          red[lr * 3 + 2] = px;
+          __builtin_amdgcn_wave_barrier();
+          if (lr == 0) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int l = 0; l < kRowLanes; ++l) {
+              s0 += red[l * 3 + 0];
+              s1 += red[l * 3 + 1];
+              s2 += red[l * 3 + 2];
+            }
+            cpart[(size_t)task * 4 + 0] = s0;
+            cpart[(size_t)task * 4 + 1] = s1;
+            cpart[(size_t)task * 4 + 2] = s2;
+          }
+          __builtin_amdgcn_wave_barrier();
         }
       }
       // in strict mode this row's atomics complete before it stages its
@@ -443,27 +486,6 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
     }
   }
 
-  if (MODE == kSweep && a.part) {
-    // fixed-order reduction of the row's FP64 partials through LDS
-    double* red = reinterpret_cast<double*>(base);
-    __builtin_amdgcn_wave_barrier();
-    red[lr * 3 + 0] = acc_num;
-    red[lr * 3 + 1] = acc_den;
-    red[lr * 3 + 2] = acc_x2;
-    __builtin_amdgcn_wave_barrier();
-    if (lr == 0 && row_ok) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      for (int l = 0; l < kRowLanes; ++l) {
-        s0 += red[l * 3 + 0];
-        s1 += red[l * 3 + 1];
-        s2 += red[l * 3 + 2];
-      }
-      a.part[(size_t)row * 4 + 0] = s0;
-      a.part[(size_t)row * 4 + 1] = s1;
-      a.part[(size_t)row * 4 + 2] = s2;
-      a.part[(size_t)row * 4 + 3] = 0.0;
-    }
-  }
 }
 
 template <int MODE, int SV, bool F16V>
