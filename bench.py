@@ -123,9 +123,8 @@ def main():
                           "launches": 3}))
         return
     import mace_inputs as mi
-    from paper_1911_09278_amd import build as libbuild
-    if not os.path.exists(libbuild.LIB):
-        libbuild.build()
+    from __graft_entry__ import _ensure_built
+    _ensure_built()
     import paper_1911_09278_amd as m
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"

@@ -193,8 +193,10 @@ int mace_get_error_sinogram(const mace_system* sys, float* e);
 
 /*
  * Scale of every ICD coordinate step, gamma in (0, 1]: z_s += gamma * alpha_s.
- * Default: 1 for the sequential schedule, 0.5 when super-voxels of an agent
- * run concurrently.  gamma = 1 is Algorithm 2's exact coordinate minimisation
+ * Default: 1 when the system runs the sequential schedule (rows_per_agent =
+ * 1, or an image too small for more), else 0.5 -- also for batches and
+ * served scans that share the rows and fall back to one row per (scan,
+ * agent), because the colour-phase visiting order is not raster order.  gamma = 1 is Algorithm 2's exact coordinate minimisation
  * (of the prior's quadratic majoriser); gamma < 1 under-relaxes the partial
  * update.  A pixel is left unchanged exactly when its coordinate derivative
  * vanishes for any gamma, so the fixed points -- and, by Theorem 1, the MAP
@@ -211,6 +213,10 @@ int mace_set_timing(mace_system* sys, int32_t enable);
 /* Bytes of repacked system matrix held on the device. */
 int64_t mace_system_bytes(const mace_system* sys);
 
+/* Device bytes of one scan's state (w, X, e, Lambda, y, theta2 of every agent,
+ * residual partials): what a batch slot or an admitted served scan holds. */
+int64_t mace_scan_bytes(const mace_system* sys);
+
 /*
  * Host-only dry run of mace_load_system for the same arguments: builds the
  * device tables and the super-voxel schedules in host memory and checks every
@@ -221,6 +227,55 @@ int64_t mace_system_bytes(const mace_system* sys);
 int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
                       const float* val, int32_t n_agents, const int32_t* view_to_agent,
                       const mace_opts* opts, int64_t* lds_bytes);
+
+/*
+ * Reconstruction service (continuous batching).  A server drives the given
+ * systems (one per scanner geometry; each may appear once, must outlive the
+ * server and must not be used by other calls while the server exists).
+ * Scans are submitted at any time; a worker thread per system admits them
+ * oldest first into scan slots while the device memory of the admitted scans'
+ * state (w, X, e, Lambda, y, theta2 per agent: mace_server_stats reports the
+ * bytes) stays within hbm_budget_bytes (0 = no limit); a scan whose state
+ * alone exceeds the budget fails with MACE_E_NOMEM, and one that does not fit
+ * yet waits, holding back later scans so that it is not starved.  Every Mann
+ * iteration (Algorithm 1) runs over all admitted scans of a system that share
+ * (prior, rho, sigma, sweeps) in one round of launches; each scan stops on its
+ * own when r_k < tol or after max_iters iterations, and a waiting scan takes
+ * the free slot at the next iteration.  The systems' iterations run on their
+ * own streams and overlap on the GPU.  A scan's result does not depend on the
+ * other scans in flight beyond the iterates (the fixed point is the same).
+ */
+typedef struct mace_server mace_server;
+
+typedef struct {
+  int64_t submitted, completed, queued;
+  int32_t in_flight, max_in_flight;    /* scans admitted and not finished */
+  int64_t bytes_in_use, peak_bytes;    /* device bytes of admitted scans' state */
+} mace_server_counters;
+
+/* Starts the worker threads.  Errors: MACE_E_ARG. */
+int mace_server_create(mace_system* const* systems, int32_t n_systems, int64_t hbm_budget_bytes,
+                       mace_server** out);
+
+/* Queues one scan of systems[system_idx] (y, lambda: host, copied before the
+ * call returns); *ticket identifies it.  max_iters >= 1; tol >= 0 (0: run
+ * max_iters iterations).  Errors: MACE_E_ARG, or the server's failure code. */
+int mace_server_submit(mace_server* srv, int32_t system_idx, const float* y, const float* lambda,
+                       const mace_prior* prior, double rho, double sigma, int32_t sweeps,
+                       double tol, int32_t max_iters, int64_t* ticket);
+
+/* Blocks until the scan has finished; x_out[nx*ny] (may be NULL) receives its
+ * image, info its statistics, *latency_s the time from submit to finish.  A
+ * ticket can be waited for once.  Returns the scan's status (MACE_OK,
+ * MACE_W_MAXITER, or an error such as MACE_E_NOMEM / MACE_E_NONFINITE). */
+int mace_server_wait(mace_server* srv, int64_t ticket, float* x_out, mace_info* info,
+                     double* latency_s);
+
+/* Counters of the server; returns MACE_OK or the server's failure code. */
+int mace_server_stats(mace_server* srv, mace_server_counters* out);
+
+/* Finishes the scans in flight, drops the waiting ones, stops the workers. */
+void mace_server_destroy(mace_server* srv);
 
 void mace_free_system(mace_system* sys);
 const char* mace_last_error(void);

@@ -56,6 +56,13 @@ class Info(ctypes.Structure):
                 ("iter_ms", ctypes.c_double)]
 
 
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int32),
+                ("max_in_flight", ctypes.c_int32), ("bytes_in_use", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_1911_09278_amd.build.build()")
@@ -86,8 +93,20 @@ def _load():
     L.mace_set_timing.restype = ctypes.c_int
     L.mace_system_bytes.argtypes = [vp]
     L.mace_system_bytes.restype = i64
+    L.mace_scan_bytes.argtypes = [vp]
+    L.mace_scan_bytes.restype = i64
     L.mace_check_layout.argtypes = [P(Geom), vp, vp, vp, i32, vp, P(Opts), vp]
     L.mace_check_layout.restype = ctypes.c_int
+    L.mace_server_create.argtypes = [vp, i32, i64, P(vp)]
+    L.mace_server_create.restype = ctypes.c_int
+    L.mace_server_submit.argtypes = [vp, i32, vp, vp, P(Prior), d, d, i32, d, i32, P(i64)]
+    L.mace_server_submit.restype = ctypes.c_int
+    L.mace_server_wait.argtypes = [vp, i64, vp, P(Info), P(d)]
+    L.mace_server_wait.restype = ctypes.c_int
+    L.mace_server_stats.argtypes = [vp, P(ServerCounters)]
+    L.mace_server_stats.restype = ctypes.c_int
+    L.mace_server_destroy.argtypes = [vp]
+    L.mace_server_destroy.restype = None
     L.mace_free_system.argtypes = [vp]
     L.mace_free_system.restype = None
     L.mace_last_error.argtypes = []
@@ -99,9 +118,10 @@ _lib = _load()
 
 # Entry points of the C ABI, by name.
 EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_dev", "mace_solve_batch",
-            "mace_solve_batch_dev", "mace_prox", "mace_visit_order",
-            "mace_get_state", "mace_get_error_sinogram", "mace_system_bytes", "mace_check_layout", "mace_set_timing",
-            "mace_set_relaxation",
+            "mace_solve_batch_dev", "mace_prox", "mace_visit_order", "mace_get_state",
+            "mace_get_error_sinogram", "mace_system_bytes", "mace_scan_bytes",
+            "mace_check_layout", "mace_set_timing", "mace_set_relaxation", "mace_server_create",
+            "mace_server_submit", "mace_server_wait", "mace_server_stats", "mace_server_destroy",
             "mace_free_system", "mace_last_error")
 
 
@@ -174,6 +194,11 @@ class System:
     @property
     def matrix_bytes(self) -> int:
         return int(_lib.mace_system_bytes(self._h))
+
+    @property
+    def scan_bytes(self) -> int:
+        """Device bytes of one scan's state (a batch slot / a served scan)."""
+        return int(_lib.mace_scan_bytes(self._h))
 
     def solve(self, y, lam, prior: Prior, rho, sigma, max_iters, tol=0.0, sweeps=1,
               w_init=None):
@@ -272,3 +297,54 @@ class System:
         X = np.empty(self.N * self.n, dtype=np.float32)
         _check(_lib.mace_get_state(self._h, _ptr(w), _ptr(X)))
         return w.reshape(self.N, self.n), X.reshape(self.N, self.n)
+
+
+class Server:
+    """Continuous-batching reconstruction service over loaded systems.
+
+    The systems must stay open while the server exists and must not be used
+    by other calls meanwhile.  submit() returns at once; wait() blocks for one
+    scan (ctypes releases the GIL during the call)."""
+
+    def __init__(self, systems, hbm_budget_bytes=0):
+        self._h = None
+        self.systems = list(systems)
+        arr = (ctypes.c_void_p * len(self.systems))(*[s._h.value for s in self.systems])
+        h = ctypes.c_void_p()
+        _check(_lib.mace_server_create(arr, len(self.systems), int(hbm_budget_bytes),
+                                       ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, system_idx, y, lam, prior: Prior, rho, sigma, tol, max_iters, sweeps=1):
+        s = self.systems[system_idx]
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        ll = np.ascontiguousarray(lam, dtype=np.float32)
+        if yy.size != s.n_rows or ll.size != s.n_rows:
+            raise ValueError("y / lambda have the wrong size")
+        t = ctypes.c_int64(0)
+        _check(_lib.mace_server_submit(self._h, int(system_idx), _ptr(yy), _ptr(ll),
+                                       ctypes.byref(prior), float(rho), float(sigma), int(sweeps),
+                                       float(tol), int(max_iters), ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket, n_pixels):
+        """Returns (x, info, latency_s); raises MaceError if the scan failed."""
+        x = np.empty(int(n_pixels), dtype=np.float32)
+        info = Info()
+        lat = ctypes.c_double(0.0)
+        _check(_lib.mace_server_wait(self._h, int(ticket), _ptr(x), ctypes.byref(info),
+                                     ctypes.byref(lat)))
+        return x, info, float(lat.value)
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(_lib.mace_server_stats(self._h, ctypes.byref(c)))
+        return {f: int(getattr(c, f)) for f, _ in ServerCounters._fields_}
+
+    def close(self):
+        if self._h:
+            _lib.mace_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

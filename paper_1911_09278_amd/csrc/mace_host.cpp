@@ -35,7 +35,7 @@ const std::string& last_error_text() { return g_err; }
 extern "C" const char* mace_last_error(void) { return g_err.c_str(); }
 
 mace_system::~mace_system() {
-  graphs.clear();
+  batch.graphs.clear();
   for (auto e : ev) (void)hipEventDestroy(e);
   if (stream) (void)hipStreamDestroy(stream);
 }
@@ -515,7 +515,7 @@ void mace::fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, doub
   a.band = s->band.p;
   a.band_rows = s->band_rows.p;
   a.estride = s->estride;
-  a.slots = s->table.p;
+  a.slots = s->batch.table.p;
   a.invN = (float)(1.0 / s->N);
   a.relax = (float)(s->relax > 0.0 ? s->relax : (default_rows_per_agent(s) == 1 ? 1.0 : 0.5));
   a.rho = (float)rho;
@@ -596,6 +596,7 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
   if (sv_lds_bytes(s->bmax, s->S, s->kpad) > 160 * 1024)
     return fail(MACE_E_ARG, "super-voxel band needs %zu bytes of LDS per workgroup; use a smaller sv_size",
                 sv_lds_bytes(s->bmax, s->S, s->kpad));
+  HIP_OK(hipGetDevice(&s->device));
   HIP_OK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
   *out = s.release();
   g_err.clear();

@@ -90,5 +90,7 @@ hipError_t launch_fill(float* dst, float v, int64_t count, hipStream_t st);
 hipError_t launch_broadcast_mean(const float* w, float* wbar, float* X, int N, int n,
                                  hipStream_t st);
 hipError_t launch_copy(float* dst, const float* src, int64_t count, hipStream_t st);
+// table[i] = d, ordered on the stream (the descriptor travels as a kernel argument).
+hipError_t launch_write_slot(SlotDesc* table, int i, SlotDesc d, hipStream_t st);
 
 }  // namespace mace

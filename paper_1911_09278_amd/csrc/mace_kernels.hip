@@ -142,4 +142,13 @@ hipError_t launch_broadcast_mean(const float* w, float* wbar, float* X, int N, i
   return hipGetLastError();
 }
 
+__global__ void write_slot_kernel(SlotDesc* table, int i, SlotDesc d) {
+  if (threadIdx.x == 0) table[i] = d;
+}
+
+hipError_t launch_write_slot(SlotDesc* table, int i, SlotDesc d, hipStream_t st) {
+  hipLaunchKernelGGL(write_slot_kernel, dim3(1), dim3(64), 0, st, table, i, d);
+  return hipGetLastError();
+}
+
 }  // namespace mace

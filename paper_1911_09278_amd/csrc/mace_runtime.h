@@ -81,6 +81,17 @@ struct IterGraph {
   }
 };
 
+// A set of scan slots that advance together: slot table, residual read-back,
+// captured iteration graphs.  A system holds one for its own solves; a
+// server holds one per group of scans that share the solver parameters.
+struct Batch {
+  std::vector<std::unique_ptr<ScanSlot>> scan;
+  DevBuf<SlotDesc> table;  // device slot table, kMaxScanSlots entries
+  std::vector<SlotDesc> htable;
+  DevBuf<double> lastres;  // latest residual of each slot
+  std::map<std::tuple<int, int, int, int, uint64_t>, std::unique_ptr<IterGraph>> graphs;
+};
+
 }  // namespace mace
 
 struct mace_system {
@@ -108,13 +119,10 @@ struct mace_system {
   mace::DevBuf<int> d_sv_pix0;
   mace::DevBuf<int> row_src;  // agent-block row -> global row (or -1)
   std::map<std::tuple<int, int, int>, std::unique_ptr<mace::Schedule>> schedules;
-  // scan slots: slot 0 serves mace_solve / mace_prox; batches use 0..B-1
-  std::vector<std::unique_ptr<mace::ScanSlot>> scan;
-  mace::DevBuf<mace::SlotDesc> table;  // device slot table
-  std::vector<mace::SlotDesc> htable;
-  mace::DevBuf<double> lastres;
+  // slot 0 serves mace_solve / mace_prox; mace_solve_batch uses 0..B-1
+  mace::Batch batch;
   hipStream_t stream = nullptr;
-  std::map<std::tuple<int, int, int, int, uint64_t>, std::unique_ptr<mace::IterGraph>> graphs;
+  int device = 0;  // HIP device the system lives on
   int64_t matrix_bytes = 0;
   bool timing = false;
   double relax = 0.0;  // 0: automatic (1 for the sequential schedule, 0.5 otherwise)
@@ -128,4 +136,19 @@ Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P);
 int check_prior(const mace_prior* pr);
 void fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, double rho, double sigma,
                bool fp16);
+
+// Scan-slot machinery (mace_solve.cpp), shared by the batch solve and the server.
+int64_t slot_bytes(const mace_system* s, int resid_cap);
+int ensure_slot(mace_system* s, Batch& b, int idx, int resid_cap);
+void release_slot(Batch& b, int idx);
+// Writes the device table entry of slot i (stream-ordered, by a kernel).
+int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st);
+int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam,
+               const float* w_init, const SvArgs& base, hipStream_t st);
+int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, const SvArgs& base,
+                  bool theta2, hipStream_t st);
+int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, const SvArgs& a,
+                  int sweeps, int P, hipStream_t st);
+// Rows per (scan, agent) when n scans run together.
+int batch_rows_per_agent(const mace_system* s, int n);
 }  // namespace mace

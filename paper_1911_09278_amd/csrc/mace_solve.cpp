@@ -16,11 +16,17 @@
 
 using namespace mace;
 
-namespace {
+namespace mace {
 
-int ensure_slot(mace_system* s, int idx, int max_iters) {
-  while ((int)s->scan.size() <= idx) s->scan.push_back(std::make_unique<ScanSlot>());
-  ScanSlot& q = *s->scan[idx];
+int64_t slot_bytes(const mace_system* s, int resid_cap) {
+  const int64_t nimg = (int64_t)s->N * s->n, nrow = (int64_t)s->N * s->estride;
+  return 4 * (3 * nrow + 3 * nimg + s->n) + 8 * ((int64_t)s->N * s->n_sv * 4 + std::max(1, resid_cap)) + 4;
+}
+
+int ensure_slot(mace_system* s, Batch& b, int idx, int resid_cap) {
+  if (idx >= kMaxScanSlots) return fail(MACE_E_ARG, "slot %d out of range", idx);
+  while ((int)b.scan.size() <= idx) b.scan.push_back(std::make_unique<ScanSlot>());
+  ScanSlot& q = *b.scan[idx];
   const size_t nimg = (size_t)s->N * s->n;
   const size_t nrow = (size_t)s->N * s->estride;
   if (q.e.count != nrow) {
@@ -34,24 +40,30 @@ int ensure_slot(mace_system* s, int idx, int max_iters) {
     HIP_OK(q.part.alloc((size_t)s->N * s->n_sv * 4));
     HIP_OK(q.counter.alloc(1));
   }
-  const int cap = std::max(1, max_iters);
+  const int cap = std::max(1, resid_cap);
   if (q.resid_cap < cap) {
     HIP_OK(q.resid.alloc((size_t)cap));
     q.resid_cap = cap;
   }
+  // allocated once at the maximum size: captured graphs hold these addresses
+  if (b.lastres.count < (size_t)kMaxScanSlots) HIP_OK(b.lastres.alloc(kMaxScanSlots));
+  if (b.table.count < (size_t)kMaxScanSlots) {
+    HIP_OK(b.table.alloc(kMaxScanSlots));
+    b.htable.assign(kMaxScanSlots, SlotDesc{});
+    HIP_OK(hipMemset(b.table.p, 0, b.table.bytes()));  // every slot inactive
+  }
   return MACE_OK;
 }
 
-// Device slot table for slots [0, n) with the given active flags.
-int upload_table(mace_system* s, int n, const std::vector<int>& active, hipStream_t st) {
-  // allocated once at the maximum size: captured graphs hold these addresses
-  if (s->lastres.count < (size_t)kMaxScanSlots) HIP_OK(s->lastres.alloc(kMaxScanSlots));
-  if (s->table.count < (size_t)kMaxScanSlots) HIP_OK(s->table.alloc(kMaxScanSlots));
-  if (n > kMaxScanSlots) return fail(MACE_E_ARG, "too many scan slots");
-  s->htable.assign(n, SlotDesc{});
-  for (int i = 0; i < n; ++i) {
-    ScanSlot& q = *s->scan[i];
-    SlotDesc& d = s->htable[i];
+void release_slot(Batch& b, int idx) {
+  if (idx < (int)b.scan.size()) b.scan[idx] = std::make_unique<ScanSlot>();
+}
+
+int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st) {
+  (void)s;
+  SlotDesc d{};
+  if (active) {
+    ScanSlot& q = *b.scan[i];
     d.e = q.e.p;
     d.lam = q.lam.p;
     d.X = q.X.p;
@@ -60,24 +72,22 @@ int upload_table(mace_system* s, int n, const std::vector<int>& active, hipStrea
     d.th2 = q.th2.p;
     d.part = q.part.p;
     d.resid = q.resid.p;
-    d.last = s->lastres.p + i;
+    d.last = b.lastres.p + i;
     d.counter = q.counter.p;
     d.resid_cap = q.resid_cap;
-    d.active = active[i];
+    d.active = 1;
   }
-  HIP_OK(hipMemcpyAsync(s->table.p, s->htable.data(), sizeof(SlotDesc) * n, hipMemcpyHostToDevice, st));
+  b.htable[i] = d;
+  HIP_OK(launch_write_slot(b.table.p, i, d, st));
   return MACE_OK;
 }
 
-int set_active(mace_system* s, int i, int on, hipStream_t st) {
-  s->htable[i].active = on;
-  HIP_OK(hipMemcpyAsync(&s->table.p[i].active, &s->htable[i].active, sizeof(int),
-                        hipMemcpyHostToDevice, st));
-  return MACE_OK;
-}
+}  // namespace mace
 
-// Sweep-mode launches over all four colour phases (mode kTheta2 / kRefresh
-// for set-up), with the slot table seen from `slot_base`.
+namespace {
+
+// Launches over all four colour phases in one mode, with the slot table seen
+// from `slot_base`.
 int launch_phases(mace_system* s, const Schedule* sch, SvArgs a, int mode, hipStream_t st,
                   const SlotDesc* slot_base) {
   const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
@@ -91,61 +101,13 @@ int launch_phases(mace_system* s, const Schedule* sch, SvArgs a, int mode, hipSt
   return MACE_OK;
 }
 
-// Load y / Lambda (device, global row order) of slot i and set its initial
-// state: w = w_init (or 0), X = G(w), e = y - A X, theta2; residual counter 0.
-int start_slot(mace_system* s, int i, const float* y, const float* lam, const float* w_init,
-               const SvArgs& base, hipStream_t st) {
-  ScanSlot& q = *s->scan[i];
-  const int64_t nrow = (int64_t)s->N * s->estride;
-  HIP_OK(launch_gather_rows(q.yb.p, y, s->row_src.p, nrow, st));
-  HIP_OK(launch_copy(q.e.p, q.yb.p, nrow, st));
-  HIP_OK(launch_gather_rows(q.lam.p, lam, s->row_src.p, nrow, st));
-  const int64_t nimg = (int64_t)s->N * s->n;
-  if (w_init)
-    HIP_OK(launch_copy(q.w.p, w_init, nimg, st));
-  else
-    HIP_OK(launch_fill(q.w.p, 0.f, nimg, st));
-  HIP_OK(launch_broadcast_mean(q.w.p, q.wbar.p, q.X.p, s->N, s->n, st));
-  HIP_OK(hipMemsetAsync(q.counter.p, 0, sizeof(int), st));
-  // theta2 (and e = y - A X when X != 0) through a one-slot schedule that
-  // sees the table from this slot on
-  const int P = default_rows_per_agent(s);
-  Schedule* one = get_schedule(s, 1, -1, P);
-  if (!one) return fail(MACE_E_HIP, "schedule upload failed");
-  SvArgs a = base;
-  a.strict = P == 1 ? 1 : 0;
-  int rc = launch_phases(s, one, a, kTheta2, st, s->table.p + i);
-  if (rc) return rc;
-  if (w_init) {
-    rc = launch_phases(s, one, a, kRefresh, st, s->table.p + i);
-    if (rc) return rc;
-  }
-  return MACE_OK;
-}
-
-// e = y - A X for every active slot of the batch (FP32 drift), and theta2 too
-// when the matrix values change precision.
-int refresh_batch(mace_system* s, int n_slots, const Schedule* sch, const SvArgs& base,
-                  bool theta2, hipStream_t st) {
-  for (int i = 0; i < n_slots; ++i) {
-    if (!s->htable[i].active) continue;
-    ScanSlot& q = *s->scan[i];
-    HIP_OK(launch_copy(q.e.p, q.yb.p, (int64_t)s->N * s->estride, st));
-  }
-  if (theta2) {
-    int rc = launch_phases(s, sch, base, kTheta2, st, s->table.p);
-    if (rc) return rc;
-  }
-  return launch_phases(s, sch, base, kRefresh, st, s->table.p);
-}
-
 // The launches of one Mann iteration: `sweeps` ICD passes (the last one with
 // the reflection + Mann update) and the epilogue.
-int enqueue_iteration(mace_system* s, const Schedule* sch, int n_slots, SvArgs a, int sweeps,
-                      hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+int enqueue_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, SvArgs a,
+                      int sweeps, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
   a.R = sch->R;
-  a.slots = s->table.p;
+  a.slots = b.table.p;
   if (ev0) HIP_OK(hipEventRecord(ev0, st));
   for (int sw = 0; sw < sweeps; ++sw) {
     a.mann = (sw == sweeps - 1) ? 1 : 0;
@@ -156,7 +118,7 @@ int enqueue_iteration(mace_system* s, const Schedule* sch, int n_slots, SvArgs a
     }
   }
   if (ev1) HIP_OK(hipEventRecord(ev1, st));
-  HIP_OK(launch_epilogue(s->table.p, n_slots, s->N, s->n, s->N * s->n_sv, st));
+  HIP_OK(launch_epilogue(b.table.p, n_slots, s->N, s->n, s->N * s->n_sv, st));
   return MACE_OK;
 }
 
@@ -174,22 +136,77 @@ uint64_t args_key(const SvArgs& a) {
   return h;
 }
 
+}  // namespace
+
+namespace mace {
+
+// Theta2 = sum_r A_rs^2 Lambda_r and, from y and w_init, the initial state of
+// slot i: w = w_init (or 0), X = G(w), e = y - A X (y, lam: device, global
+// row order).  The slot's table entry is written and switched on.
+int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam,
+               const float* w_init, const SvArgs& base, hipStream_t st) {
+  ScanSlot& q = *b.scan[i];
+  const int64_t nrow = (int64_t)s->N * s->estride;
+  HIP_OK(launch_gather_rows(q.yb.p, y, s->row_src.p, nrow, st));
+  HIP_OK(launch_copy(q.e.p, q.yb.p, nrow, st));
+  HIP_OK(launch_gather_rows(q.lam.p, lam, s->row_src.p, nrow, st));
+  const int64_t nimg = (int64_t)s->N * s->n;
+  if (w_init)
+    HIP_OK(launch_copy(q.w.p, w_init, nimg, st));
+  else
+    HIP_OK(launch_fill(q.w.p, 0.f, nimg, st));
+  HIP_OK(launch_broadcast_mean(q.w.p, q.wbar.p, q.X.p, s->N, s->n, st));
+  HIP_OK(hipMemsetAsync(q.counter.p, 0, sizeof(int), st));
+  HIP_OK(hipMemsetAsync(b.lastres.p + i, 0, sizeof(double), st));
+  int rc = write_slot(s, b, i, 1, st);
+  if (rc) return rc;
+  // theta2 (and e = y - A X when X != 0) through a one-slot schedule that
+  // sees the table from this slot on
+  const int P = default_rows_per_agent(s);
+  Schedule* one = get_schedule(s, 1, -1, P);
+  if (!one) return fail(MACE_E_HIP, "schedule upload failed");
+  SvArgs a = base;
+  a.strict = P == 1 ? 1 : 0;
+  rc = launch_phases(s, one, a, kTheta2, st, b.table.p + i);
+  if (rc) return rc;
+  if (w_init) {
+    rc = launch_phases(s, one, a, kRefresh, st, b.table.p + i);
+    if (rc) return rc;
+  }
+  return MACE_OK;
+}
+
+// e = y - A X for every active slot (FP32 drift), and theta2 too when the
+// matrix values change precision.
+int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, const SvArgs& base,
+                  bool theta2, hipStream_t st) {
+  for (int i = 0; i < n_slots; ++i) {
+    if (!b.htable[i].active) continue;
+    ScanSlot& q = *b.scan[i];
+    HIP_OK(launch_copy(q.e.p, q.yb.p, (int64_t)s->N * s->estride, st));
+  }
+  if (theta2) {
+    int rc = launch_phases(s, sch, base, kTheta2, st, b.table.p);
+    if (rc) return rc;
+  }
+  return launch_phases(s, sch, base, kRefresh, st, b.table.p);
+}
+
 // One Mann iteration through a captured graph.  The first iteration with a
 // given configuration runs eagerly (it also performs the one-time kernel
 // attribute set-up, which stays out of the capture); the second captures.
-int run_iteration_graph(mace_system* s, const Schedule* sch, int n_slots, const SvArgs& a,
-                        int sweeps, int P, hipStream_t st) {
-  const auto key = std::make_tuple(n_slots, P, sweeps, s->precision, args_key(a));
-  auto it = s->graphs.find(key);
-  IterGraph* g = nullptr;
-  if (it == s->graphs.end()) {
-    s->graphs[key] = nullptr;
-    return enqueue_iteration(s, sch, n_slots, a, sweeps, st, nullptr, nullptr);
+int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, const SvArgs& a,
+                  int sweeps, int P, hipStream_t st) {
+  const auto key = std::make_tuple(n_slots, P, sweeps, a.fp16, args_key(a));
+  auto it = b.graphs.find(key);
+  if (it == b.graphs.end()) {
+    b.graphs[key] = nullptr;
+    return enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
   }
   if (!it->second) {
     auto ng = std::make_unique<IterGraph>();
     HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_iteration(s, sch, n_slots, a, sweeps, st, nullptr, nullptr);
+    int rc = enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(st, &graph);
     if (rc) {
@@ -199,14 +216,21 @@ int run_iteration_graph(mace_system* s, const Schedule* sch, int n_slots, const 
     HIP_OK(e);
     ng->graph = graph;
     HIP_OK(hipGraphInstantiate(&ng->exec, graph, nullptr, nullptr, 0));
-    g = ng.get();
-    s->graphs[key] = std::move(ng);
-  } else {
-    g = it->second.get();
+    it->second = std::move(ng);
   }
-  HIP_OK(hipGraphLaunch(g->exec, st));
+  HIP_OK(hipGraphLaunch(it->second->exec, st));
   return MACE_OK;
 }
+
+int batch_rows_per_agent(const mace_system* s, int n) {
+  const int P = default_rows_per_agent(s);
+  if (s->rows_per_agent > 0 || n <= 1) return P;
+  return std::max(1, P / n);
+}
+
+}  // namespace mace
+
+namespace {
 
 struct BatchIO {
   const float* y;
@@ -230,30 +254,29 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
   if (max_iters < 0) return fail(MACE_E_ARG, "max_iters must be >= 0");
   for (int i = 0; i < n; ++i)
     if (!io[i].y || !io[i].lam || !io[i].x_out) return fail(MACE_E_ARG, "NULL scan argument");
+  Batch& b = s->batch;
   hipStream_t st = s->stream;
   if (user) HIP_OK(hipStreamSynchronize(user));  // the caller's inputs are ready
-  // concurrency per (scan, agent): keep about the same number of rows in total
-  int P = default_rows_per_agent(s);
-  if (n > 1 && s->rows_per_agent == 0) P = std::max(1, P / n);
+  const int P = batch_rows_per_agent(s, n);
   Schedule* sch = get_schedule(s, n, -1, P);
   if (!sch) return fail(MACE_E_HIP, "schedule upload failed");
   for (int i = 0; i < n; ++i) {
-    rc = ensure_slot(s, i, max_iters);
+    rc = ensure_slot(s, b, i, max_iters);
     if (rc) return rc;
   }
-  std::vector<int> active(n, 1);
-  rc = upload_table(s, n, active, st);
-  if (rc) return rc;
   const bool fp16 = s->precision == 1;
   SvArgs a;
   fill_args(s, a, pr, rho, sigma, fp16);
   a.strict = P == 1 ? 1 : 0;
-  if (s->relax <= 0.0) a.relax = P == 1 ? 1.0f : 0.5f;
   for (int i = 0; i < n; ++i) {
-    rc = start_slot(s, i, io[i].y, io[i].lam, io[i].w_init, a, st);
+    rc = start_slot(s, b, i, io[i].y, io[i].lam, io[i].w_init, a, st);
     if (rc) return rc;
   }
-  HIP_OK(hipMemsetAsync(s->lastres.p, 0, sizeof(double) * n, st));
+  for (int i = n; i < (int)b.htable.size(); ++i)
+    if (b.htable[i].active) {
+      rc = write_slot(s, b, i, 0, st);
+      if (rc) return rc;
+    }
   const bool timing = s->timing;
   if (timing && (int)s->ev.size() < 2 * max_iters + 2) {
     for (auto e : s->ev) (void)hipEventDestroy(e);
@@ -271,28 +294,28 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
       // switch to FP32 values: rebuild e = y - A X and theta2 with them
       a.fp16 = 0;
       tail_done = true;
-      rc = refresh_batch(s, n, sch, a, true, st);
+      rc = refresh_slots(s, b, n, sch, a, true, st);
       if (rc) return rc;
     } else if (s->refresh_every > 0 && it > 0 && it % s->refresh_every == 0) {
-      rc = refresh_batch(s, n, sch, a, false, st);
+      rc = refresh_slots(s, b, n, sch, a, false, st);
       if (rc) return rc;
     }
     if (timing)
-      rc = enqueue_iteration(s, sch, n, a, sweeps, st, s->ev[2 * it], s->ev[2 * it + 1]);
+      rc = enqueue_iteration(s, b, sch, n, a, sweeps, st, s->ev[2 * it], s->ev[2 * it + 1]);
     else
-      rc = run_iteration_graph(s, sch, n, a, sweeps, P, st);
+      rc = run_iteration(s, b, sch, n, a, sweeps, P, st);
     if (rc) return rc;
     for (int i = 0; i < n; ++i)
-      if (s->htable[i].active) iters[i] = it + 1;
+      if (b.htable[i].active) iters[i] = it + 1;
     if (tol > 0) {
-      HIP_OK(hipMemcpyAsync(last.data(), s->lastres.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipMemcpyAsync(last.data(), b.lastres.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
       for (int i = 0; i < n; ++i) {
-        if (!s->htable[i].active) continue;
+        if (!b.htable[i].active) continue;
         const bool bad = !std::isfinite(last[i]);
         if (bad || last[i] < tol) {
           if (bad) status[i] = MACE_E_NONFINITE;
-          rc = set_active(s, i, 0, st);
+          rc = write_slot(s, b, i, 0, st);
           if (rc) return rc;
           --live;
         }
@@ -300,7 +323,7 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
     }
   }
   if (timing) HIP_OK(hipEventRecord(s->ev[2 * max_iters + 1], st));
-  HIP_OK(hipMemcpyAsync(last.data(), s->lastres.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(last.data(), b.lastres.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   double sweep_ms = 0.0, iter_ms = 0.0;
   if (timing) {
@@ -315,7 +338,7 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
   }
   int worst = MACE_OK;
   for (int i = 0; i < n; ++i) {
-    ScanSlot& q = *s->scan[i];
+    ScanSlot& q = *b.scan[i];
     if (max_iters == 0) HIP_OK(launch_broadcast_mean(q.w.p, q.wbar.p, q.X.p, s->N, s->n, st));
     // x = mean_i w_i: wbar holds it after the scan's last epilogue
     HIP_OK(hipMemcpyAsync(io[i].x_out, q.wbar.p, sizeof(float) * s->n, hipMemcpyDeviceToDevice, st));
@@ -422,12 +445,13 @@ extern "C" int mace_prox(mace_system* s, int32_t agent, const float* y, const fl
   const int P = default_rows_per_agent(s);
   Schedule* sch = get_schedule(s, 1, agent, P);
   if (!sch) return fail(MACE_E_HIP, "schedule upload failed");
-  rc = ensure_slot(s, 0, 1);
+  Batch& b = s->batch;
+  rc = ensure_slot(s, b, 0, 1);
   if (rc) return rc;
   hipStream_t st = s->stream;
-  rc = upload_table(s, 1, std::vector<int>{1}, st);
+  rc = write_slot(s, b, 0, 1, st);
   if (rc) return rc;
-  ScanSlot& q = *s->scan[0];
+  ScanSlot& q = *b.scan[0];
   const size_t m = (size_t)s->n_views * s->n_ch;
   const int64_t nrow = (int64_t)s->N * s->estride;
   DevBuf<float> dy, dl, dv;
@@ -447,13 +471,13 @@ extern "C" int mace_prox(mace_system* s, int32_t agent, const float* y, const fl
   SvArgs a;
   fill_args(s, a, pr, 0.5, sigma, fp16);
   a.strict = P == 1 ? 1 : 0;
-  rc = launch_phases(s, sch, a, kTheta2, st, s->table.p);
+  rc = launch_phases(s, sch, a, kTheta2, st, b.table.p);
   if (rc) return rc;
-  rc = launch_phases(s, sch, a, kRefresh, st, s->table.p);
+  rc = launch_phases(s, sch, a, kRefresh, st, b.table.p);
   if (rc) return rc;
   a.mann = 0;
   for (int sw = 0; sw < sweeps; ++sw) {
-    rc = launch_phases(s, sch, a, kSweep, st, s->table.p);
+    rc = launch_phases(s, sch, a, kSweep, st, b.table.p);
     if (rc) return rc;
   }
   HIP_OK(hipMemcpyAsync(x_out, q.X.p + (size_t)agent * s->n, sizeof(float) * s->n,
@@ -462,19 +486,23 @@ extern "C" int mace_prox(mace_system* s, int32_t agent, const float* y, const fl
   return MACE_OK;
 }
 
+extern "C" int64_t mace_scan_bytes(const mace_system* s) { return s ? slot_bytes(s, 1) : 0; }
+
 extern "C" int mace_get_state(const mace_system* s, float* w, float* X) {
   if (!s) return fail(MACE_E_ARG, "NULL system");
-  if (s->scan.empty() || !s->scan[0]->w.p) return fail(MACE_E_ARG, "no solve has run on this system");
+  if (s->batch.scan.empty() || !s->batch.scan[0]->w.p)
+    return fail(MACE_E_ARG, "no solve has run on this system");
   const size_t bytes = (size_t)s->N * s->n * sizeof(float);
-  if (w) HIP_OK(hipMemcpy(w, s->scan[0]->w.p, bytes, hipMemcpyDeviceToHost));
-  if (X) HIP_OK(hipMemcpy(X, s->scan[0]->X.p, bytes, hipMemcpyDeviceToHost));
+  if (w) HIP_OK(hipMemcpy(w, s->batch.scan[0]->w.p, bytes, hipMemcpyDeviceToHost));
+  if (X) HIP_OK(hipMemcpy(X, s->batch.scan[0]->X.p, bytes, hipMemcpyDeviceToHost));
   return MACE_OK;
 }
 
 extern "C" int mace_get_error_sinogram(const mace_system* s, float* e) {
   if (!s || !e) return fail(MACE_E_ARG, "NULL argument");
-  if (s->scan.empty() || !s->scan[0]->e.p) return fail(MACE_E_ARG, "no solve has run on this system");
-  const ScanSlot& q = *s->scan[0];
+  if (s->batch.scan.empty() || !s->batch.scan[0]->e.p)
+    return fail(MACE_E_ARG, "no solve has run on this system");
+  const ScanSlot& q = *s->batch.scan[0];
   std::vector<float> blk(q.e.count);
   HIP_OK(hipMemcpy(blk.data(), q.e.p, q.e.bytes(), hipMemcpyDeviceToHost));
   for (int a = 0; a < s->N; ++a)

@@ -29,6 +29,7 @@
 // launch.  Kernel boundaries make all changes of a phase visible to the next.
 // The coordinate step is scaled by `relax` (1: the exact minimiser of the
 // surrogate; below 1: an under-relaxed step with the same fixed points).
+#include <atomic>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
@@ -493,13 +494,13 @@ inline hipError_t launch_mode(const SvArgs& a, int slots, int grid, size_t lds, 
   switch (slots) {
 #define MACE_CASE(SLV)                                                                   \
   case SLV: {                                                                            \
-    static bool attr_set = false;                                                        \
-    if (!attr_set) {                                                                     \
+    static std::atomic<bool> attr_set{false};                                            \
+    if (!attr_set.load(std::memory_order_acquire)) {                                     \
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel<SLV, MODE, SV, F16V>), \
                                          hipFuncAttributeMaxDynamicSharedMemorySize,     \
                                          160 * 1024);                                    \
       if (e != hipSuccess) return e;                                                     \
-      attr_set = true;                                                                   \
+      attr_set.store(true, std::memory_order_release);                                   \
     }                                                                                    \
     hipLaunchKernelGGL((sv_kernel<SLV, MODE, SV, F16V>), dim3(grid), dim3(kBlockThreads), lds, st, a); \
     break;                                                                               \

@@ -127,3 +127,22 @@ def test_device_layout_scan512():
     cp, row, val = mi.system_matrix(g)
     lds = m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents)
     assert lds <= 160 * 1024
+
+
+def test_server_rejects_bad_arguments_without_a_device():
+    import ctypes
+    import paper_1911_09278_amd as m
+    L = m._lib
+    h = ctypes.c_void_p()
+    assert L.mace_server_create(None, 0, 0, ctypes.byref(h)) == m.MACE_E_ARG
+    assert not h.value
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.mace_server_create(arr, 1, 0, ctypes.byref(h)) == m.MACE_E_ARG
+    t = ctypes.c_int64(0)
+    pr = m.make_prior(0, 0.01)
+    assert L.mace_server_submit(None, 0, None, None, ctypes.byref(pr), 0.8, 0.01, 1, 0.0, 10,
+                                ctypes.byref(t)) == m.MACE_E_ARG
+    assert L.mace_server_wait(None, 1, None, None, None) == m.MACE_E_ARG
+    assert L.mace_server_stats(None, None) == m.MACE_E_ARG
+    L.mace_server_destroy(None)
+    assert L.mace_scan_bytes(None) == 0

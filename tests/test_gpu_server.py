@@ -1,0 +1,143 @@
+"""GPU tests of the reconstruction service (continuous batching).
+
+1. A mix of scans of two geometries, submitted at once: every scan's result
+   equals its result alone (NRMSE <= 1e-4 between converged images, the FP32
+   bar) and, for the quadratic prior, the dense MAP; the scans overlapped.
+2. HBM-budget admission: with room for one scan's state, scans run one at a
+   time and the bytes in use never exceed the budget; a scan larger than the
+   budget fails with MACE_E_NOMEM while the others complete.
+3. Scans with different solver parameters run in separate groups of one
+   system and still match their alone results.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import mace_inputs as mi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1911_09278_amd as lib
+    return lib
+
+
+def _nrmse(a, b):
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+GA = mi.Geometry(32, 32, 64, 48)
+GB = mi.Geometry(48, 48, 96, 72)
+SX, SIGMA, TOL = 0.001, 0.001, 1e-6
+
+
+def _system(m, g, N=4):
+    cp, row, val = mi.system_matrix(g)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N)
+    return sysm, (cp, row, val)
+
+
+def test_mix_equals_alone(m):
+    from tests import dense_ref as dr
+    sa, (cpa, rowa, vala) = _system(m, GA)
+    sb, _ = _system(m, GB)
+    prior = m.make_prior(0, SX)
+    jobs = [(0, mi.scan(GA, 31)), (1, mi.scan(GB, 32)), (0, mi.scan(GA, 33)),
+            (1, mi.scan(GB, 34)), (0, mi.scan(GA, 35))]
+    systems = [sa, sb]
+    print("alone runs", flush=True)
+    alone = []
+    for k, s in jobs:
+        x, info = systems[k].solve(s.y, s.lam, prior, 0.8, SIGMA, 4000, tol=TOL)
+        assert info.status == m.MACE_OK
+        alone.append(x)
+    print("served mix", flush=True)
+    srv = m.Server(systems)
+    try:
+        tickets = [srv.submit(k, s.y, s.lam, prior, 0.8, SIGMA, TOL, 4000) for k, s in jobs]
+        out = [srv.wait(t, systems[k].n) for t, (k, _) in zip(tickets, jobs)]
+        st = srv.stats()
+    finally:
+        srv.close()
+    print(st, flush=True)
+    assert st["completed"] == len(jobs) and st["max_in_flight"] >= 2
+    A = dr.dense_A(GA, cpa, rowa, vala)
+    L = dr.laplacian(GA.nx, GA.ny)
+    for (k, s), (x, info, lat), xa in zip(jobs, out, alone):
+        print(k, info.iters, info.residual, f"{lat * 1e3:.1f} ms", _nrmse(x, xa), flush=True)
+        assert info.status == m.MACE_OK and info.residual < TOL
+        assert lat > 0
+        assert _nrmse(x, xa) <= 1e-4
+        if k == 0:
+            xmap = dr.map_quadratic(A, s.lam.astype(np.float64), s.y.astype(np.float64), L, SX)
+            assert _nrmse(x, xmap) <= 1e-4
+
+
+def test_budget_admission_and_oversized_scan(m):
+    sa, _ = _system(m, GA)
+    prior = m.make_prior(0, SX)
+    budget = int(sa.scan_bytes * 1.5)  # room for one scan's state
+    big = mi.Geometry(96, 96, 128, 140)
+    sc, _ = _system(m, big)
+    assert sa.scan_bytes <= budget < 2 * sa.scan_bytes < sc.scan_bytes
+    systems = [sa, sc]
+    srv = m.Server(systems, hbm_budget_bytes=budget)
+    try:
+        scans = [(0, mi.scan(GA, 41)), (1, mi.scan(big, 43)), (0, mi.scan(GA, 42)),
+                 (0, mi.scan(GA, 44))]
+        tickets = [srv.submit(k, s.y, s.lam, prior, 0.8, SIGMA, 1e-4, 2000) for k, s in scans]
+        results = []
+        for t, (k, _) in zip(tickets, scans):
+            try:
+                results.append(srv.wait(t, systems[k].n))
+            except m.MaceError as e:
+                results.append(e)
+        st = srv.stats()
+    finally:
+        srv.close()
+    print(st, flush=True)
+    assert isinstance(results[1], m.MaceError) and results[1].code == m.MACE_E_NOMEM
+    for i in (0, 2, 3):
+        x, info, _ = results[i]
+        assert info.status == m.MACE_OK and np.all(np.isfinite(x))
+    assert st["peak_bytes"] <= budget
+    assert st["max_in_flight"] == 1
+    assert st["completed"] == 3
+
+
+def test_groups_with_different_parameters(m):
+    sa, _ = _system(m, GA)
+    p1 = m.make_prior(0, SX)
+    p2 = m.make_prior(0, 0.0015)
+    s1, s2 = mi.scan(GA, 51), mi.scan(GA, 52)
+    x1a, i1a = sa.solve(s1.y, s1.lam, p1, 0.8, SIGMA, 4000, tol=TOL)
+    assert i1a.status == m.MACE_OK
+    x2a, i2a = sa.solve(s2.y, s2.lam, p2, 0.8, SIGMA, 4000, tol=TOL)
+    assert i2a.status == m.MACE_OK
+    srv = m.Server([sa])
+    got = {}
+    try:
+        t1 = srv.submit(0, s1.y, s1.lam, p1, 0.8, SIGMA, TOL, 4000)
+        # the second scan arrives while the first is in flight
+
+        def later():
+            time.sleep(0.002)
+            got["t2"] = srv.submit(0, s2.y, s2.lam, p2, 0.8, SIGMA, TOL, 4000)
+        th = threading.Thread(target=later)
+        th.start()
+        th.join()
+        x1, i1, _ = srv.wait(t1, GA.n)
+        x2, i2, _ = srv.wait(got["t2"], GA.n)
+    finally:
+        srv.close()
+    print(i1.iters, i1.residual, i2.iters, i2.residual, flush=True)
+    assert i1.status == m.MACE_OK and i2.status == m.MACE_OK
+    assert _nrmse(x1, x1a) <= 1e-4
+    assert _nrmse(x2, x2a) <= 1e-4
