@@ -96,7 +96,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=60)
-    ap.add_argument("--sigma", type=float, default=2e-4)
+    ap.add_argument("--sigma", type=float, default=1e-4)
     ap.add_argument("--rows-per-agent", type=int, default=0)
     ap.add_argument("--sv-size", type=int, default=0)
     ap.add_argument("--relax", type=float, default=0.5)

@@ -332,7 +332,11 @@ static int check_pack(const mace_system* s, const HostPack& hp) {
       int rows = 0;
       for (int kl = 0; kl < kpad; ++kl) {
         const BandEnt& b = hp.band[asv * kpad + kl];
-        if (b.width == 0) continue;
+        if (b.width == 0) {
+          // the kernel reads entry gstart of an empty band
+          if (b.gstart != 0) return fail(MACE_E_MATRIX, "check: empty band with gstart %u", b.gstart);
+          continue;
+        }
         if (kl >= K) return fail(MACE_E_MATRIX, "check: band entry on a padding view");
         if ((int)b.lds_row + b.width > B) return fail(MACE_E_MATRIX, "check: band overruns its rows");
         if ((int64_t)b.gstart + b.width > K * s->n_ch) return fail(MACE_E_MATRIX, "check: band leaves the agent block");

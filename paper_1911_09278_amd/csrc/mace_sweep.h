@@ -79,7 +79,8 @@ __device__ __forceinline__ float2 load_vals(const SvArgs& a, size_t idx, float s
 
 // Record of one pixel for the lane's view slots: (a0, a1) on channels d0,
 // d0 + 1 and the LDS row of d0.
-constexpr int kPrefetch = 4;
+constexpr int kPrefetch = 3;
+constexpr int kFlushGroup = 16;  // views per group in the band write-back
 
 template <int SL>
 struct Rec {
@@ -119,57 +120,77 @@ __device__ __forceinline__ void load_rec_at(const float2* vb, const __half2* hb,
   }
 }
 
-// LDS bytes of one row: band (e, Lambda) and the staged copy of e over bmax
-// rows, the halo tile (value, inside-image flag), v and theta2 of the SV.
+// The staged copy of e that the write-back subtracts lives in registers for
+// up to 64 views per agent, in LDS beyond that.
+__host__ __device__ constexpr bool e0_in_lds(int kpad) { return kpad > 4 * kRowLanes; }
+
+// Halo cells of an S x S super-voxel, padded to whole 16-lane groups.
+__host__ __device__ constexpr int halo_cells(int S) {
+  return ((S + 2) * (S + 2) + kRowLanes - 1) / kRowLanes * kRowLanes;
+}
+
+// LDS bytes of one row: band (e, Lambda) over bmax rows, the staged copy of e
+// when it does not stay in registers, the halo tile of the agent image, and a
+// scratch area that holds the task's band entries while its band is staged,
+// then v and theta2 of the SV's pixels.
 __host__ __device__ inline size_t row_lds_bytes(int bmax, int S, int kpad) {
-  const size_t HS = S + 2;
-  const size_t per_row = (size_t)bmax * 12 + HS * HS * 8 + (size_t)S * S * 8 + (size_t)kpad * 8;
+  const size_t scratch = (size_t)S * S * 8 > (size_t)kpad * 8 ? (size_t)S * S * 8 : (size_t)kpad * 8;
+  size_t per_row = (size_t)bmax * 8 + (e0_in_lds(kpad) ? (size_t)bmax * 4 : 0) +
+                   (size_t)halo_cells(S) * 4 + scratch;
+  per_row = (per_row + 7) & ~(size_t)7;
   const size_t red = kRowLanes * 3 * sizeof(double);  // per-task FP64 reduction
   return per_row > red ? per_row : red;
 }
 
-// Everything a row needs to start its next task, loaded into registers while
-// the current task's pixels are being updated.
-template <int SL, int S, int WM>
-struct Stage {
-  static constexpr int HS = S + 2;
-  static constexpr int HC = (HS * HS + kRowLanes - 1) / kRowLanes;  // halo cells per lane
-  static constexpr int PPL = (S * S + kRowLanes - 1) / kRowLanes;   // pixels per lane
-  int task;   // agent * n_sv + sv, or -1
-  int B;
-  int pix0;
-  float* e;   // the task's slot: error sinogram, agent state, Mann state,
-  float* X;   // theta2 and residual partials
-  float* w;
-  float* th2;
-  double* part;
-  BandEnt be[SL];
-  float ev[SL][WM];
-  float lv[SL][WM];
-  float hv[HC];
-  float wo[PPL];  // w of the agent before the update
-  float wb[PPL];  // consensus average w-bar
-  float t2[PPL];
+// Per-scan buffers reached through the slot table are global memory; saying
+// so keeps their accesses off the flat path (whose loads also count as LDS
+// operations and would stall the LDS waits of the pixel loop).
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
+// Error-sinogram entries are read at agent scope (from L2): other rows add
+// their changes there with atomics during the launch.
+__device__ __forceinline__ float load_e(gptr<const float> p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_e(gptr<float> p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Two waves per SIMD when the register budget allows it: the second wave's
+// instructions fill the first one's LDS and dependency stalls.
+template <int SL>
+struct Occupancy {
+  static constexpr int waves = SL <= 3 ? 2 : 1;
 };
 
 template <int SL, int MODE, int S, bool F16>
-__global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
-  constexpr int WM = (S <= 4) ? 8 : 16;
+__global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel(SvArgs a) {
   constexpr int HS = S + 2;
-  using St = Stage<SL, S, WM>;
+  constexpr int KP = SL * kRowLanes;                                 // view slots
+  constexpr int HC = halo_cells(S) / kRowLanes;                     // halo cells per lane
+  constexpr int PPL = (S * S + kRowLanes - 1) / kRowLanes;          // pixels per lane
+  static_assert(PPL * kRowLanes == S * S, "a row covers the SV's pixels in whole lane groups");
+  constexpr bool kE0Lds = e0_in_lds(KP);
+  constexpr bool kE0Reg = MODE == kSweep && !kE0Lds;
   extern __shared__ __align__(16) char smem[];
   const int lane64 = threadIdx.x & 63;
   const int lr = lane64 & 15;
   const int rib = ((threadIdx.x >> 6) << 2) | (lane64 >> 4);  // row in block
   const int row = blockIdx.x * kRowsPerBlock + rib;
-  const size_t per_row = row_lds_bytes(a.bmax, S, a.kpad);
+  const size_t per_row = row_lds_bytes(a.bmax, S, KP);
   char* base = smem + rib * per_row;
   float2* band = reinterpret_cast<float2*>(base);
-  float* e0 = reinterpret_cast<float*>(base + (size_t)a.bmax * 8);
-  float2* halo = reinterpret_cast<float2*>(base + (size_t)a.bmax * 12);
-  float* vv = reinterpret_cast<float*>(base + (size_t)a.bmax * 12 + (size_t)HS * HS * 8);
+  float* e0l = reinterpret_cast<float*>(base + (size_t)a.bmax * 8);  // kE0Lds only
+  float* halo = reinterpret_cast<float*>(base + (size_t)a.bmax * (kE0Lds ? 12 : 8));
+  float* vv = halo + halo_cells(S);
   float* t2 = vv + S * S;
-  BandEnt* bents = reinterpret_cast<BandEnt*>(t2 + S * S);  // [kpad]
+  BandEnt* bents = reinterpret_cast<BandEnt*>(vv);  // while the band is staged
 
   // neighbour of lanes 0-7: (di, dj) in raster order of the 3x3 block
   const int ndi = (lr < 3) ? -1 : (lr < 5 ? 0 : 1);
@@ -177,317 +198,336 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel(SvArgs a) {
   // lanes 8-15 carry no neighbour: zero weight, offset 0 (their own cell)
   const float nbw = lr < 8 ? ((ndi != 0 && ndj != 0) ? a.bdiag : a.bedge) * a.invN : 0.0f;
   const int noff = lr < 8 ? ndi * HS + ndj : 0;
+  const int ndi8 = lr < 8 ? ndi : 0, ndj8 = lr < 8 ? ndj : 0;
   const float proxw = lr == 8 ? a.is2 : 0.0f;  // lane 8 adds the prox term
 
   const bool row_ok = row < a.R;
-  // strict: this row sees every earlier task's changes (one SV of an agent
-  // at a time); otherwise the next band may be staged before the current
-  // task's changes land
   const bool strict = a.strict != 0;
+  const int* my_tasks = a.tasks + (size_t)(row_ok ? row : 0) * a.T;
 
-  // ---- staging of task t into registers ----
-  auto stage_load = [&](int t, St& st) {
-    const int raw = (row_ok && t < a.T) ? a.tasks[(size_t)row * a.T + t] : -1;
-    st.task = -1;
+  // Header of a task: everything its id determines (issued one task ahead).
+  struct Hdr {
+    int task;  // agent * n_sv + sv, or -1
+    gptr<float> e;
+    gptr<const float> lam;
+    gptr<float> X, w, th2;
+    gptr<const float> wbar;
+    gptr<double> part;
+    int B, pix0;
+    BandEnt cb[SL];  // the lane's band entries (view slots lr, lr + 16, ...)
+  };
+  auto load_hdr = [&](int raw, Hdr& h) {
+    h.task = -1;
     if (raw < 0) return;
-    const int local = raw & ((1 << kSlotShift) - 1);
+    const int task = raw & ((1 << kSlotShift) - 1);
     const SlotDesc* sd = a.slots + (raw >> kSlotShift);
-    const int agent = local / a.n_sv;
-    const int sv = local - agent * a.n_sv;
+    const int agent = task / a.n_sv;
+    const int sv = task - agent * a.n_sv;
+    const size_t agent_sv = (size_t)agent * a.n_sv + sv;
+    const BandEnt* be = a.band + agent_sv * KP;
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) h.cb[sl] = be[sl * kRowLanes + lr];
+    h.B = a.band_rows[agent_sv];
+    h.pix0 = a.sv_pix0[sv];
+    h.e = glb(sd->e) + (size_t)agent * a.estride;
+    h.lam = glb(sd->lam) + (size_t)agent * a.estride;
+    h.X = glb(sd->X);
+    h.w = glb(sd->w);
+    h.wbar = glb(sd->wbar);
+    h.th2 = glb(sd->th2);
+    h.part = glb(sd->part);
+    if (sd->active) h.task = task;
+  };
+  // Stage task h in LDS: its band (e, Lambda) with the 16 lanes on
+  // consecutive channels of one view at a time, the halo tile of the agent
+  // image, v = 2 w-bar - w and theta2 of its pixels; e as staged stays in e0
+  // (registers or LDS) for the write-back, w and w-bar in wo / wb.
+  auto stage = [&](const Hdr& h, float* e0r, float* wo, float* wb) {
+    if (h.task < 0) return;
+    const int agent = h.task / a.n_sv;
+    const int sv = h.task - agent * a.n_sv;
     const int sy = sv / a.gx, sx = sv - sy * a.gx;
     const int y0 = sy * S, x0 = sx * S;
-    const int sh = min(S, a.ny - y0), sw = min(S, a.nx - x0);
-    const size_t agent_sv = (size_t)agent * a.n_sv + sv;
-    const BandEnt* be = a.band + agent_sv * a.kpad;
+    const int sw = min(S, a.nx - x0);
+    const int npix = min(S, a.ny - y0) * sw;
     const size_t img = (size_t)agent * a.n;
-    // slot pointers and the task's tables are independent loads
-    float* se = sd->e;
-    const float* slam = sd->lam;
-    float* sX = sd->X;
-    float* sw_ = sd->w;
-    const float* swb = sd->wbar;
-    float* sth2 = sd->th2;
-    double* spart = sd->part;
-    const int sactive = sd->active;
-    st.B = a.band_rows[agent_sv];
-    st.pix0 = a.sv_pix0[sv];
+    float ev[KP], lv[KP];
+    float hv[HC], t2v[PPL];
 #pragma unroll
-    for (int sl = 0; sl < SL; ++sl) st.be[sl] = be[sl * kRowLanes + lr];
-    if (!sactive) return;
-    st.task = local;
-    st.e = se;
-    st.X = sX;
-    st.w = sw_;
-    st.th2 = sth2;
-    st.part = spart;
-    const float* eag = se + (size_t)agent * a.estride;
-    const float* lag = slam + (size_t)agent * a.estride;
+    for (int sl = 0; sl < SL; ++sl) bents[sl * kRowLanes + lr] = h.cb[sl];
+    __builtin_amdgcn_wave_barrier();
+    // No branches: lanes past a view's band re-read its last channel (an
+    // empty band has gstart 0), so every address is valid whatever the lane
+    // and the entry's fields are used unconditionally.
+    const uint2* bent2 = reinterpret_cast<const uint2*>(bents);
 #pragma unroll
-    for (int sl = 0; sl < SL; ++sl) {
-      const int wdt = min((int)st.be[sl].width, WM);
-#pragma unroll
-      for (int c = 0; c < WM; ++c) {
-        st.ev[sl][c] = 0.0f;
-        st.lv[sl][c] = 0.0f;
-        if (c < wdt) {
-          if (MODE == kSweep && !strict) st.ev[sl][c] = eag[st.be[sl].gstart + c];
-          if (MODE != kRefresh) st.lv[sl][c] = lag[st.be[sl].gstart + c];
-        }
-      }
+    for (int k = 0; k < KP; ++k) {
+      const uint2 b = bent2[k];  // (gstart, lds_row | width << 16)
+      const int wd = (int)(b.y >> 16);
+      const uint32_t gi = b.x + (uint32_t)min(lr, max(wd - 1, 0));
+      // values of lanes past the band go to the throw-away cell below and
+      // are never subtracted in the write-back
+      ev[k] = MODE == kSweep ? load_e(h.e + gi) : 0.0f;
+      lv[k] = MODE != kRefresh ? h.lam[gi] : 0.0f;
     }
     if (MODE != kTheta2) {
 #pragma unroll
-      for (int u = 0; u < St::HC; ++u) {
+      for (int u = 0; u < HC; ++u) {
+        // cells past HS * HS are padding; every load reads a pixel inside
+        // the image and out-of-image cells are zeroed
         const int c = u * kRowLanes + lr;
         const int hi = c / HS, hj = c - (c / HS) * HS;
         const int iy = y0 - 1 + hi, ix = x0 - 1 + hj;
-        const bool in = c < HS * HS && iy >= 0 && iy < a.ny && ix >= 0 && ix < a.nx;
-        st.hv[u] = in ? sX[img + (size_t)iy * a.nx + ix] : 0.0f;
+        const bool in = iy >= 0 && iy < a.ny && ix >= 0 && ix < a.nx;
+        const int iyc = min(max(iy, 0), a.ny - 1), ixc = min(max(ix, 0), a.nx - 1);
+        const float xv = h.X[img + (size_t)iyc * a.nx + ixc];
+        hv[u] = in ? xv : 0.0f;
       }
     }
     if (MODE == kSweep) {
 #pragma unroll
-      for (int u = 0; u < St::PPL; ++u) {
+      for (int u = 0; u < PPL; ++u) {
+        // PPL * 16 == S * S; entries past npix (ragged SVs) repeat the last
+        // pixel and are never read
         const int p = u * kRowLanes + lr;
-        st.wo[u] = 0.0f;
-        st.wb[u] = 0.0f;
-        st.t2[u] = 0.0f;
-        if (p < sh * sw) {
-          const int pi = p / sw, pj = p - (p / sw) * sw;
-          const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
-          st.wb[u] = swb[pix];
-          st.wo[u] = sw_[img + pix];
-          st.t2[u] = sth2[img + pix];
-        }
+        const int pc = min(p, npix - 1);
+        const int pi = pc / sw, pj = pc - (pc / sw) * sw;
+        const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
+        wb[u] = h.wbar[pix];
+        wo[u] = h.w[img + pix];
+        t2v[u] = h.th2[img + pix];
+      }
+    }
+    // LDS writes; lanes past a view's band write to a throw-away cell (the
+    // halo, written last).  The band entries are read again rather than
+    // kept in registers (the empty asm keeps the compiler from reusing the
+    // first reads).
+    asm volatile("" ::: "memory");
+    float2* trash2 = reinterpret_cast<float2*>(halo);
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+      const uint2 b = bent2[k];
+      const int wd = (int)(b.y >> 16), lrow = (int)(b.y & 0xFFFFu);
+      float2* dst = lr < wd ? band + lrow + lr : trash2;
+      *dst = make_float2(ev[k], lv[k]);
+      if constexpr (kE0Lds && MODE == kSweep) {
+        float* d0 = lr < wd ? e0l + lrow + lr : reinterpret_cast<float*>(trash2);
+        *d0 = ev[k];
+      }
+      if constexpr (kE0Reg) e0r[k] = ev[k];
+    }
+    if (lr < 2) band[h.B + lr] = make_float2(0.0f, 0.0f);
+    if (MODE != kTheta2) {
+#pragma unroll
+      for (int u = 0; u < HC; ++u) halo[u * kRowLanes + lr] = hv[u];
+    }
+    if (MODE == kSweep) {
+      __builtin_amdgcn_wave_barrier();  // v / theta2 overwrite the band entries
+#pragma unroll
+      for (int u = 0; u < PPL; ++u) {
+        const int p = u * kRowLanes + lr;
+        vv[p] = 2.0f * wb[u] - wo[u];
+        t2[p] = t2v[u];
       }
     }
   };
 
-  St st;
-  stage_load(0, st);
+  Hdr h;
+  load_hdr((row_ok && a.T > 0) ? my_tasks[0] : -1, h);
+  int raw_next = (row_ok && a.T > 1) ? my_tasks[1] : -1;
   for (int t = 0; t < a.T; ++t) {
-    // current task from the stage
-    const int task = st.task;
-    if (task >= 0) {
-      const int agent = task / a.n_sv;
-      const int sv = task - agent * a.n_sv;
-      const int sy = sv / a.gx, sx = sv - sy * a.gx;
-      const int y0 = sy * S, x0 = sx * S;
-      const int sh = min(S, a.ny - y0), sw = min(S, a.nx - x0);
-      const int npix = sh * sw;
-      const size_t agent_sv = (size_t)agent * a.n_sv + sv;
-      const BandEnt* be = a.band + agent_sv * a.kpad;
-      const int B = st.B;
-      float* eag = st.e + (size_t)agent * a.estride;
-      float* cX = st.X;
-      float* cw = st.w;
-      float* cth2 = st.th2;
-      double* cpart = st.part;
-      const size_t img = (size_t)agent * a.n;
-      BandEnt cb[SL];
+    const Hdr cur = h;
+    // ---- 1. stage the task ----
+    float e0r[kE0Reg ? KP : 1];
+    float cwo[PPL], cwb[PPL];
+    stage(cur, e0r, cwo, cwb);
+    __builtin_amdgcn_wave_barrier();
+    // header of the next task, loaded behind this task's pixel loop
+    load_hdr(raw_next, h);
+    raw_next = (row_ok && t + 2 < a.T) ? my_tasks[t + 2] : -1;
+    if (cur.task < 0) continue;
+    const int task = cur.task;
+    const int agent = task / a.n_sv;
+    const int sv = task - agent * a.n_sv;
+    const int sy = sv / a.gx, sx = sv - sy * a.gx;
+    const int y0 = sy * S, x0 = sx * S;
+    const int sh = min(S, a.ny - y0), sw = min(S, a.nx - x0);
+    const int npix = sh * sw;
+    const size_t img = (size_t)agent * a.n;
+    const int pix0 = cur.pix0;
+    gptr<float> eag = cur.e;
+    gptr<float> cX = cur.X;
+    gptr<float> cw = cur.w;
+    gptr<float> cth2 = cur.th2;
+    gptr<double> cpart = cur.part;
 
-      // ---- 1. commit the staged task to LDS ----
-#pragma unroll
-      for (int sl = 0; sl < SL; ++sl) {
-        cb[sl] = st.be[sl];
-        const int wdt = (int)cb[sl].width;
-        float ev[WM];
-#pragma unroll
-        for (int c = 0; c < WM; ++c) ev[c] = st.ev[sl][c];
-        if (MODE == kSweep && strict) {
-#pragma unroll
-          for (int c = 0; c < WM; ++c)
-            if (c < wdt) ev[c] = eag[cb[sl].gstart + c];
-        }
-#pragma unroll
-        for (int c = 0; c < WM; ++c)
-          if (c < wdt) {
-            band[cb[sl].lds_row + c] = make_float2(ev[c], st.lv[sl][c]);
-            if (MODE == kSweep) e0[cb[sl].lds_row + c] = ev[c];
-          }
-      }
-      if (lr < 2) band[B + lr] = make_float2(0.0f, 0.0f);
-      if (MODE != kTheta2) {
-#pragma unroll
-        for (int u = 0; u < St::HC; ++u) {
-          const int c = u * kRowLanes + lr;
-          if (c < HS * HS) {
-            const int hi = c / HS, hj = c - (c / HS) * HS;
-            const int iy = y0 - 1 + hi, ix = x0 - 1 + hj;
-            const bool in = iy >= 0 && iy < a.ny && ix >= 0 && ix < a.nx;
-            halo[c] = make_float2(st.hv[u], in ? 1.0f : 0.0f);
-          }
-        }
-      }
-      float cwo[St::PPL], cwb[St::PPL];
+    // ---- 2. pixel loop: records prefetched kPrefetch pixels ahead ----
+    const size_t rec0 = (size_t)agent * a.n + pix0;
+    auto update = [&](const Rec<SL>& cur, int j, int pi, int pj) {
+      const int cidx = (pi + 1) * HS + pj + 1;
       if (MODE == kSweep) {
+        // every LDS read of this pixel first, then the arithmetic
+        float2 p0[SL], p1[SL];
 #pragma unroll
-        for (int u = 0; u < St::PPL; ++u) {
-          const int p = u * kRowLanes + lr;
-          cwo[u] = st.wo[u];
-          cwb[u] = st.wb[u];
-          if (p < npix) {
-            vv[p] = 2.0f * cwb[u] - cwo[u];
-            t2[p] = st.t2[u];
-          }
+        for (int s2 = 0; s2 < SL; ++s2) {
+          p0[s2] = band[cur.off[s2]];
+          p1[s2] = band[cur.off[s2] + 1];
+        }
+        const float zs = halo[cidx];
+        const float nbv = halo[cidx + noff];
+        const float vj = vv[j], tj = t2[j];
+        // the neighbour lies in the image (lanes 8-15: weight 0 anyway)
+        const int iy = y0 + pi + ndi8, ix = x0 + pj + ndj8;
+        const float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+        float part = 0.0f;
+#pragma unroll
+        for (int s2 = 0; s2 < SL; ++s2)
+          part += cur.val[s2].x * p0[s2].y * p0[s2].x + cur.val[s2].y * p1[s2].y * p1[s2].x;
+        const float d = zs - nbv;
+        const float wgt = nbw * nin * prior_curv(a, d);
+        const float gl = wgt * d + proxw * (zs - vj) - part;
+        const float G = row_sum16(gl);
+        const float H = row_sum16(wgt);
+        const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(tj + H + a.is2);
+#pragma unroll
+        for (int s2 = 0; s2 < SL; ++s2) {
+          band[cur.off[s2]].x = p0[s2].x - cur.val[s2].x * alpha;
+          band[cur.off[s2] + 1].x = p1[s2].x - cur.val[s2].y * alpha;
+        }
+        if (lr == 0) halo[cidx] = zs + alpha;
+      } else if (MODE == kTheta2) {
+        float part = 0.0f;
+#pragma unroll
+        for (int s2 = 0; s2 < SL; ++s2) {
+          const float l0 = band[cur.off[s2]].y, l1 = band[cur.off[s2] + 1].y;
+          part += cur.val[s2].x * cur.val[s2].x * l0 + cur.val[s2].y * cur.val[s2].y * l1;
+        }
+        const float th = row_sum16(part);
+        if (lr == 0) {
+          const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
+          cth2[img + pix] = th;
+        }
+      } else {  // kRefresh: accumulate -A x into the band
+        const float xs = halo[cidx];
+#pragma unroll
+        for (int s2 = 0; s2 < SL; ++s2) {
+          band[cur.off[s2]].x -= cur.val[s2].x * xs;
+          band[cur.off[s2] + 1].x -= cur.val[s2].y * xs;
         }
       }
-      const int pix0 = st.pix0;
       __builtin_amdgcn_wave_barrier();
-
-      // ---- 2. pixel loop: records prefetched kPrefetch pixels ahead; the
-      //         next task is staged right after the first pixel ----
-      const size_t rec0 = (size_t)agent * a.n + pix0;
-      auto update = [&](const Rec<SL>& cur, int j, int pi, int pj) {
-        const int cidx = (pi + 1) * HS + pj + 1;
-        if (MODE == kSweep) {
-          // every LDS read of this pixel first, then the arithmetic
-          float2 p0[SL], p1[SL];
+    };
+    if (npix == S * S) {
+      // full super-voxel: straight-line code, every record in its own
+      // registers, so each wait covers exactly the record it needs
+      const size_t rb = rec0 * KP + lr;
+      const float2* vb = F16 ? nullptr : a.aval + rb;
+      const __half2* hb = F16 ? a.hval + rb : nullptr;
+      const float* sb = F16 ? a.hscale + rec0 : nullptr;
+      const uint16_t* ob = a.aoff + rb;
+      Rec<SL> buf[S * S];
 #pragma unroll
-          for (int s2 = 0; s2 < SL; ++s2) {
-            p0[s2] = band[cur.off[s2]];
-            p1[s2] = band[cur.off[s2] + 1];
-          }
-          const float zs = halo[cidx].x;
-          const float2 nb = halo[cidx + noff];
-          const float vj = vv[j], tj = t2[j];
-          float part = 0.0f;
+      for (int q = 0; q < kPrefetch; ++q) load_rec_at<SL, F16>(vb, hb, sb, ob, q, buf[q]);
 #pragma unroll
-          for (int s2 = 0; s2 < SL; ++s2)
-            part += cur.val[s2].x * p0[s2].y * p0[s2].x + cur.val[s2].y * p1[s2].y * p1[s2].x;
-          const float d = zs - nb.x;
-          const float wgt = nbw * nb.y * prior_curv(a, d);
-          const float gl = wgt * d + proxw * (zs - vj) - part;
-          const float G = row_sum16(gl);
-          const float H = row_sum16(wgt);
-          const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(tj + H + a.is2);
-#pragma unroll
-          for (int s2 = 0; s2 < SL; ++s2) {
-            band[cur.off[s2]].x = p0[s2].x - cur.val[s2].x * alpha;
-            band[cur.off[s2] + 1].x = p1[s2].x - cur.val[s2].y * alpha;
-          }
-          if (lr == 0) halo[cidx].x = zs + alpha;
-        } else if (MODE == kTheta2) {
-          float part = 0.0f;
-#pragma unroll
-          for (int s2 = 0; s2 < SL; ++s2) {
-            const float l0 = band[cur.off[s2]].y, l1 = band[cur.off[s2] + 1].y;
-            part += cur.val[s2].x * cur.val[s2].x * l0 + cur.val[s2].y * cur.val[s2].y * l1;
-          }
-          const float th = row_sum16(part);
-          if (lr == 0) {
-            const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
-            cth2[img + pix] = th;
-          }
-        } else {  // kRefresh: accumulate -A x into the band
-          const float xs = halo[cidx].x;
-#pragma unroll
-          for (int s2 = 0; s2 < SL; ++s2) {
-            band[cur.off[s2]].x -= cur.val[s2].x * xs;
-            band[cur.off[s2] + 1].x -= cur.val[s2].y * xs;
-          }
-        }
-        __builtin_amdgcn_wave_barrier();
-      };
-      if (npix == S * S) {
-        // full super-voxel: straight-line code, every record in its own
-        // registers, so each wait covers exactly the record it needs
-        constexpr int KP = SL * kRowLanes;
-        const size_t rb = rec0 * KP + lr;
-        const float2* vb = F16 ? nullptr : a.aval + rb;
-        const __half2* hb = F16 ? a.hval + rb : nullptr;
-        const float* sb = F16 ? a.hscale + rec0 : nullptr;
-        const uint16_t* ob = a.aoff + rb;
-        Rec<SL> buf[S * S];
-#pragma unroll
-        for (int q = 0; q < kPrefetch; ++q) load_rec_at<SL, F16>(vb, hb, sb, ob, q, buf[q]);
-#pragma unroll
-        for (int j = 0; j < S * S; ++j) {
-          if (j + kPrefetch < S * S)
-            load_rec_at<SL, F16>(vb, hb, sb, ob, j + kPrefetch, buf[j + kPrefetch]);
-          if (j == 0) stage_load(t + 1, st);
-          update(buf[j], j, j / S, j % S);
-        }
-      } else {
-        // ragged super-voxel at the image border
-        for (int j = 0; j < npix; ++j) {
-          Rec<SL> cur;
-          load_rec<SL, F16>(a, rec0 + j, lr, cur);
-          if (j == 0) stage_load(t + 1, st);
-          update(cur, j, j / sw, j - (j / sw) * sw);
-        }
+      for (int j = 0; j < S * S; ++j) {
+        if (j + kPrefetch < S * S)
+          load_rec_at<SL, F16>(vb, hb, sb, ob, j + kPrefetch, buf[j + kPrefetch]);
+        update(buf[j], j, j / S, j % S);
       }
-
-      // ---- 3. write back: the band's change goes to the agent's error
-      //         sinogram with atomics, one view per instruction, the 16 lanes
-      //         on consecutive channels (one or two cache lines each) ----
-      if (MODE != kTheta2) {
-#pragma unroll
-        for (int sl = 0; sl < SL; ++sl) bents[sl * kRowLanes + lr] = cb[sl];
-        __builtin_amdgcn_wave_barrier();
-        for (int kl = 0; kl < a.kpad; ++kl) {
-          const BandEnt b = bents[kl];
-          for (int c = lr; c < (int)b.width; c += kRowLanes) {
-            float d = band[b.lds_row + c].x;
-            if (MODE == kSweep) d -= e0[b.lds_row + c];
-            atomicAdd(eag + b.gstart + c, d);
-          }
-        }
-      }
-      if (MODE == kSweep) {
-        double pn = 0.0, pd = 0.0, px = 0.0;
-#pragma unroll
-        for (int u = 0; u < St::PPL; ++u) {
-          const int p = u * kRowLanes + lr;
-          if (p < npix) {
-            const int pi = p / sw, pj = p - (p / sw) * sw;
-            const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
-            const float xn = halo[(pi + 1) * HS + pj + 1].x;
-            cX[img + pix] = xn;
-            if (a.mann) {
-              const float wo = cwo[u], wb = cwb[u];
-              const float v = 2.0f * wb - wo;
-              cw[img + pix] = a.rho * (2.0f * xn - v) + (1.0f - a.rho) * wo;
-              const double d = (double)xn - (double)wb;
-              pn += d * d;
-              pd += (double)wo * (double)wo;
-              px += (double)xn * (double)xn;
-            }
-          }
-        }
-        if (a.mann) {
-          // the task's FP64 partials, summed over the row in a fixed order
-          // through LDS (the band is free after the flush)
-          double* red = reinterpret_cast<double*>(base);
-          __builtin_amdgcn_wave_barrier();
-          red[lr * 3 + 0] = pn;
-          red[lr * 3 + 1] = pd;
-          red[lr * 3 + 2] = px;
-          __builtin_amdgcn_wave_barrier();
-          if (lr == 0) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int l = 0; l < kRowLanes; ++l) {
-              s0 += red[l * 3 + 0];
-              s1 += red[l * 3 + 1];
-              s2 += red[l * 3 + 2];
-            }
-            cpart[(size_t)task * 4 + 0] = s0;
-            cpart[(size_t)task * 4 + 1] = s1;
-            cpart[(size_t)task * 4 + 2] = s2;
-          }
-          __builtin_amdgcn_wave_barrier();
-        }
-      }
-      // in strict mode this row's atomics complete before it stages its
-      // next band
-      if (strict) __builtin_amdgcn_s_waitcnt(0);
-      __builtin_amdgcn_wave_barrier();
     } else {
-      stage_load(t + 1, st);
+      // ragged super-voxel at the image border
+      for (int j = 0; j < npix; ++j) {
+        Rec<SL> cur;
+        load_rec<SL, F16>(a, rec0 + j, lr, cur);
+        update(cur, j, j / sw, j - (j / sw) * sw);
+      }
     }
-  }
 
+    // ---- 3. write back: the band's change goes to the agent's error
+    //         sinogram with atomics, one view per instruction, the 16 lanes
+    //         on consecutive channels (one or two cache lines each; a band
+    //         is at most 16 channels wide).  Views go in groups of
+    //         kFlushGroup so that their LDS reads overlap. ----
+    if (MODE != kTheta2) {
+      // v / theta2 are done: the scratch area holds the band entries again
+#pragma unroll
+      for (int sl = 0; sl < SL; ++sl) bents[sl * kRowLanes + lr] = cur.cb[sl];
+      __builtin_amdgcn_wave_barrier();
+      const uint2* bent2 = reinterpret_cast<const uint2*>(bents);
+#pragma unroll
+      for (int kb = 0; kb < KP; kb += kFlushGroup) {
+        uint2 b[kFlushGroup];
+        float d[kFlushGroup];
+#pragma unroll
+        for (int u = 0; u < kFlushGroup; ++u) b[u] = bent2[kb + u];
+#pragma unroll
+        for (int u = 0; u < kFlushGroup; ++u) {
+          // lanes past the band read its last row (any valid row) and add
+          // nothing
+          const int wd = (int)(b[u].y >> 16), lrow = (int)(b[u].y & 0xFFFFu);
+          const int r = lrow + min(lr, max(wd - 1, 0));
+          d[u] = band[r].x;
+          if constexpr (MODE == kSweep) {
+            if constexpr (kE0Reg) d[u] -= e0r[kb + u];
+            else d[u] -= e0l[r];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kFlushGroup; ++u)
+          if (lr < (int)(b[u].y >> 16)) add_e(eag + b[u].x + lr, d[u]);
+      }
+    }
+    if (MODE == kSweep) {
+      double pn = 0.0, pd = 0.0, px = 0.0;
+#pragma unroll
+      for (int u = 0; u < PPL; ++u) {
+        const int p = u * kRowLanes + lr;
+        if (p < npix) {
+          const int pi = p / sw, pj = p - (p / sw) * sw;
+          const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
+          const float xn = halo[(pi + 1) * HS + pj + 1];
+          cX[img + pix] = xn;
+          if (a.mann) {
+            const float wo = cwo[u], wb = cwb[u];
+            const float v = 2.0f * wb - wo;
+            cw[img + pix] = a.rho * (2.0f * xn - v) + (1.0f - a.rho) * wo;
+            const double dd = (double)xn - (double)wb;
+            pn += dd * dd;
+            pd += (double)wo * (double)wo;
+            px += (double)xn * (double)xn;
+          }
+        }
+      }
+      if (a.mann) {
+        // the task's FP64 partials, summed over the row in a fixed order
+        // through LDS (the band is free after the write-back)
+        double* red = reinterpret_cast<double*>(base);
+        __builtin_amdgcn_wave_barrier();
+        red[lr * 3 + 0] = pn;
+        red[lr * 3 + 1] = pd;
+        red[lr * 3 + 2] = px;
+        __builtin_amdgcn_wave_barrier();
+        if (lr == 0) {
+          double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+          for (int l = 0; l < kRowLanes; ++l) {
+            s0 += red[l * 3 + 0];
+            s1 += red[l * 3 + 1];
+            s2 += red[l * 3 + 2];
+          }
+          cpart[(size_t)task * 4 + 0] = s0;
+          cpart[(size_t)task * 4 + 1] = s1;
+          cpart[(size_t)task * 4 + 2] = s2;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    // sequential schedule: this row's atomics complete before it stages its
+    // next band
+    if (strict) __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
 }
+
 
 template <int MODE, int SV, bool F16V>
 inline hipError_t launch_mode(const SvArgs& a, int slots, int grid, size_t lds, hipStream_t st) {
