@@ -78,12 +78,15 @@ typedef struct {
   int32_t precision;      /* 0: A values FP32 (default); 1: FP16 with a per
                              (agent, pixel) FP32 scale */
   int32_t sv_size;        /* super-voxel side S in pixels: 4 or 8; 0 = 8 for
-                             images of at least 256 x 256 pixels, else 4 */
+                             images of at least 256 x 256 pixels, else 4;
+                             -1 = autotuned with rows_per_agent (see
+                             mace_autotune) */
   int32_t rows_per_agent; /* concurrent super-voxels per agent; 0 = automatic
-                             (about 4096 in total over the agents, at most a
-                             quarter of one colour's super-voxels); 1 =
-                             sequential (one super-voxel of an agent at a
-                             time: the visiting order of mace_visit_order) */
+                             (about 8192 in total over the agents, at most
+                             half of one colour's super-voxels -- a quarter
+                             below 256 per colour); 1 = sequential (one
+                             super-voxel of an agent at a time: the visiting
+                             order of mace_visit_order) */
   int32_t fp32_tail_iters;/* with precision 1: last iterations in FP32 A */
   int64_t hbm_budget_bytes; /* 0 = no limit */
   int32_t refresh_every;  /* recompute e = y - A X_i every this many Mann
@@ -210,12 +213,44 @@ int mace_set_relaxation(mace_system* sys, double gamma);
  * figures land in mace_info.sweep_ms / sweep_launches / iter_ms. */
 int mace_set_timing(mace_system* sys, int32_t enable);
 
+/* The configuration a loaded system runs with: precision, the super-voxel
+ * side in use, the rows per agent in use (the automatic value resolved),
+ * fp32_tail_iters and refresh_every. */
+int mace_get_config(const mace_system* sys, mace_opts* out);
+
 /* Bytes of repacked system matrix held on the device. */
 int64_t mace_system_bytes(const mace_system* sys);
 
 /* Device bytes of one scan's state (w, X, e, Lambda, y, theta2 of every agent,
  * residual partials): what a batch slot or an admitted served scan holds. */
 int64_t mace_scan_bytes(const mace_system* sys);
+
+/* One candidate configuration measured by mace_autotune. */
+typedef struct {
+  int32_t sv_size, rows_per_agent;
+  double ms_per_iter;  /* HIP-event time of one Mann iteration */
+  double residual;     /* r_k after the timed iterations */
+  int32_t status;      /* MACE_OK or MACE_E_NONFINITE */
+} mace_tune_result;
+
+/*
+ * Autotuner of the launch configuration for one geometry: for super-voxel
+ * side S in {4, 8} (those whose band fits in LDS; only base->sv_size if it
+ * is 4 or 8) and rows_per_agent in {P/4, P/2, P} below the automatic P (only
+ * base->rows_per_agent if it is set), loads the system, solves a synthetic
+ * scan (uniform 0.02/mm image, 1e4 photons, q-GGMRF prior) for `iters` timed
+ * Mann iterations and keeps the fastest time per iteration among candidates
+ * whose residual is within 1.5x of the best.  All candidates have the same
+ * fixed point (the MAP image), so they are compared at equal accuracy.  *best = *base with sv_size and rows_per_agent chosen; results
+ * (optional, up to max_results) receive every candidate, *n_results their
+ * number.  Results are cached per geometry, matrix, partition and precision
+ * for the life of the process.  mace_load_system with sv_size = -1 calls it.
+ * Errors: as mace_load_system, MACE_E_NONFINITE if no candidate stays finite.
+ */
+int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
+                  const float* val, int32_t n_agents, const int32_t* view_to_agent,
+                  const mace_opts* base, int32_t iters, mace_opts* best, double* best_ms_per_iter,
+                  mace_tune_result* results, int32_t max_results, int32_t* n_results);
 
 /*
  * Host-only dry run of mace_load_system for the same arguments: builds the

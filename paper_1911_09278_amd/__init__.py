@@ -56,6 +56,12 @@ class Info(ctypes.Structure):
                 ("iter_ms", ctypes.c_double)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("sv_size", ctypes.c_int32), ("rows_per_agent", ctypes.c_int32),
+                ("ms_per_iter", ctypes.c_double), ("residual", ctypes.c_double),
+                ("status", ctypes.c_int32)]
+
+
 class ServerCounters(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int32),
@@ -107,6 +113,11 @@ def _load():
     L.mace_server_stats.restype = ctypes.c_int
     L.mace_server_destroy.argtypes = [vp]
     L.mace_server_destroy.restype = None
+    L.mace_autotune.argtypes = [P(Geom), vp, vp, vp, i32, vp, P(Opts), i32, P(Opts),
+                                P(d), vp, i32, P(i32)]
+    L.mace_autotune.restype = ctypes.c_int
+    L.mace_get_config.argtypes = [vp, P(Opts)]
+    L.mace_get_config.restype = ctypes.c_int
     L.mace_free_system.argtypes = [vp]
     L.mace_free_system.restype = None
     L.mace_last_error.argtypes = []
@@ -122,6 +133,7 @@ EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_dev", "mace_solve_batc
             "mace_get_error_sinogram", "mace_system_bytes", "mace_scan_bytes",
             "mace_check_layout", "mace_set_timing", "mace_set_relaxation", "mace_server_create",
             "mace_server_submit", "mace_server_wait", "mace_server_stats", "mace_server_destroy",
+            "mace_autotune", "mace_get_config",
             "mace_free_system", "mace_last_error")
 
 
@@ -160,6 +172,30 @@ def check_layout(nx, ny, n_views, n_channels, col_ptr, row, val, n_agents, view_
     return int(lds.value)
 
 
+def autotune(nx, ny, n_views, n_channels, col_ptr, row, val, n_agents, view_to_agent=None,
+             precision=0, sv_size=0, rows_per_agent=0, iters=6) -> dict:
+    """Measured choice of super-voxel side and rows per agent (C ABI
+    mace_autotune).  Returns {"sv_size", "rows_per_agent", "ms_per_iter",
+    "table": [candidate dicts]}."""
+    cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+    rw = np.ascontiguousarray(row, dtype=np.int32)
+    vl = np.ascontiguousarray(val, dtype=np.float32)
+    va = None if view_to_agent is None else np.ascontiguousarray(view_to_agent, dtype=np.int32)
+    g = Geom(int(nx), int(ny), int(n_views), int(n_channels))
+    base = Opts(int(precision), int(sv_size), int(rows_per_agent), 0, 0, 0)
+    best = Opts()
+    ms = ctypes.c_double(0.0)
+    res = (TuneResult * 16)()
+    nres = ctypes.c_int32(0)
+    _check(_lib.mace_autotune(ctypes.byref(g), _ptr(cp), _ptr(rw), _ptr(vl), int(n_agents),
+                              _ptr(va), ctypes.byref(base), int(iters), ctypes.byref(best),
+                              ctypes.byref(ms), res, 16, ctypes.byref(nres)))
+    table = [{f: getattr(res[i], f) for f, _ in TuneResult._fields_}
+             for i in range(min(nres.value, 16))]
+    return {"sv_size": best.sv_size, "rows_per_agent": best.rows_per_agent,
+            "ms_per_iter": ms.value, "table": table}
+
+
 class System:
     """A loaded scanner geometry: repacked system matrix and view partition."""
 
@@ -194,6 +230,13 @@ class System:
     @property
     def matrix_bytes(self) -> int:
         return int(_lib.mace_system_bytes(self._h))
+
+    @property
+    def config(self) -> dict:
+        """Configuration in use (super-voxel side, rows per agent, ...)."""
+        o = Opts()
+        _check(_lib.mace_get_config(self._h, ctypes.byref(o)))
+        return {f: getattr(o, f) for f, _ in Opts._fields_}
 
     @property
     def scan_bytes(self) -> int:

@@ -1,0 +1,175 @@
+// Autotuner of the launch configuration: super-voxel side S and concurrent
+// super-voxels per agent (rows of 16 lanes per agent, up to the automatic
+// value, which caps the share of a colour updated at once).  Every candidate
+// solves a synthetic scan of the caller's geometry for a few Mann iterations
+// and is timed with HIP events; the fastest time per iteration wins among the
+// candidates whose residual after those iterations is within 1.5x of the
+// best.  The candidates reach the same fixed point (the MAP image, Theorem 1;
+// the under-relaxed step keeps the fixed points), so they are compared at
+// equal accuracy.  Results are cached per (geometry, matrix, partition,
+// precision) for the process.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "mace_runtime.h"
+
+using namespace mace;
+
+namespace {
+
+struct TuneKey {
+  int nx, ny, nv, nc, N, precision;
+  int64_t nnz;
+  uint64_t hash;
+  bool operator<(const TuneKey& o) const {
+    return std::memcmp(this, &o, sizeof *this) < 0;
+  }
+};
+
+struct TuneEntry {
+  int sv_size, rows_per_agent;
+  double ms;
+  std::vector<mace_tune_result> table;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune_cache;
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ULL;
+  return h;
+}
+
+}  // namespace
+
+extern "C" int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
+                             const float* val, int32_t n_agents, const int32_t* view_to_agent,
+                             const mace_opts* base, int32_t iters, mace_opts* best,
+                             double* best_ms_per_iter, mace_tune_result* results,
+                             int32_t max_results, int32_t* n_results) {
+  if (!geom || !col_ptr || !row_idx || !val || !best) return fail(MACE_E_ARG, "NULL argument");
+  if (n_agents <= 0) return fail(MACE_E_ARG, "n_agents must be > 0");
+  if (iters < 1) return fail(MACE_E_ARG, "iters must be >= 1");
+  if (geom->nx <= 0 || geom->ny <= 0 || geom->n_views <= 0 || geom->n_channels < 2)
+    return fail(MACE_E_ARG, "bad geometry");
+  mace_opts opts{};
+  if (base) opts = *base;
+  const int64_t n = (int64_t)geom->nx * geom->ny;
+  const int64_t nnz = col_ptr[n];
+  if (nnz < 0) return fail(MACE_E_MATRIX, "negative nnz");
+  // cache key: sizes, partition and a sample of the matrix
+  TuneKey key{geom->nx, geom->ny, geom->n_views, geom->n_channels, n_agents, opts.precision, nnz,
+              1469598103934665603ULL};
+  key.hash = fnv(key.hash, col_ptr, sizeof(int64_t) * (size_t)std::min<int64_t>(n + 1, 4096));
+  const int64_t stride = std::max<int64_t>(1, nnz / 4096);
+  for (int64_t i = 0; i < nnz; i += stride) {
+    key.hash = fnv(key.hash, row_idx + i, sizeof(int32_t));
+    key.hash = fnv(key.hash, val + i, sizeof(float));
+  }
+  if (view_to_agent) key.hash = fnv(key.hash, view_to_agent, sizeof(int32_t) * geom->n_views);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *best = opts;
+      best->sv_size = it->second.sv_size;
+      best->rows_per_agent = it->second.rows_per_agent;
+      if (best_ms_per_iter) *best_ms_per_iter = it->second.ms;
+      const int nr = (int)it->second.table.size();
+      if (results)
+        for (int i = 0; i < std::min(nr, (int)max_results); ++i) results[i] = it->second.table[i];
+      if (n_results) *n_results = nr;
+      return MACE_OK;
+    }
+  }
+  // synthetic scan (built once the first load has validated the matrix): a
+  // uniform 0.02 / mm image, I0 = 1e4 photons
+  const int64_t m = (int64_t)geom->n_views * geom->n_channels;
+  std::vector<float> y, lam;
+  auto make_scan = [&]() {
+    y.assign(m, 0.0f);
+    lam.resize(m);
+    for (int64_t s = 0; s < n; ++s)
+      for (int64_t k = col_ptr[s]; k < col_ptr[s + 1]; ++k) y[row_idx[k]] += 0.02f * val[k];
+    for (int64_t r = 0; r < m; ++r) lam[r] = (float)(1e4 * std::exp(-(double)y[r]));
+  };
+  mace_prior pr{1, 0.01, 2.0, 1.2, 1.0, 0.0, 0.0};
+  // prox parameter in the stable range of Theorem 2 for this image size
+  const double sigma = 0.05 / std::max(geom->nx, geom->ny);
+  std::vector<mace_tune_result> table;
+  std::vector<float> x(n);
+  for (int S : {4, 8}) {
+    if (opts.sv_size > 0 && opts.sv_size != S) continue;  // the caller fixed S
+    mace_opts o = opts;
+    o.sv_size = S;
+    o.rows_per_agent = 0;
+    mace_system* sys = nullptr;
+    int rc = mace_load_system(geom, col_ptr, row_idx, val, n_agents, view_to_agent, &o, &sys);
+    if (rc == MACE_E_ARG && S == 8) continue;  // LDS too small for this S
+    if (rc) return rc;
+    if (y.empty()) make_scan();
+    // candidates up to the automatic value, which is already capped where
+    // block-Jacobi updates of one colour lose stability
+    const int P0 = default_rows_per_agent(sys);
+    std::vector<int> cand;
+    if (opts.rows_per_agent > 0) {
+      cand.push_back(opts.rows_per_agent);
+    } else {
+      for (int P : {P0 / 4, P0 / 2, P0})
+        if (P >= 1 && std::find(cand.begin(), cand.end(), P) == cand.end()) cand.push_back(P);
+    }
+    for (int P : cand) {
+      sys->rows_per_agent = P;
+      sys->timing = false;
+      mace_info info{};
+      // warm-up (also captures the iteration graph), then the timed solve
+      rc = mace_solve(sys, y.data(), lam.data(), &pr, 0.8, sigma, 1, 2, 0.0, nullptr, x.data(), &info);
+      if (rc < 0) {
+        mace_free_system(sys);
+        return rc;
+      }
+      sys->timing = true;
+      rc = mace_solve(sys, y.data(), lam.data(), &pr, 0.8, sigma, 1, iters, 0.0, nullptr, x.data(),
+                      &info);
+      sys->timing = false;
+      if (rc < 0 && rc != MACE_E_NONFINITE) {
+        mace_free_system(sys);
+        return rc;
+      }
+      mace_tune_result tr{};
+      tr.sv_size = S;
+      tr.rows_per_agent = P;
+      tr.ms_per_iter = info.iters > 0 ? info.iter_ms / info.iters : 0.0;
+      tr.residual = info.residual;
+      tr.status = rc < 0 ? rc : MACE_OK;
+      table.push_back(tr);
+    }
+    mace_free_system(sys);
+  }
+  // equal accuracy: a candidate whose residual after the timed iterations
+  // is well above the best one's is not taken
+  double rmin = INFINITY;
+  for (const auto& tr : table)
+    if (tr.status == MACE_OK) rmin = std::min(rmin, tr.residual);
+  int bi = -1;
+  for (int i = 0; i < (int)table.size(); ++i)
+    if (table[i].status == MACE_OK && table[i].residual <= 1.5 * rmin &&
+        (bi < 0 || table[i].ms_per_iter < table[bi].ms_per_iter))
+      bi = i;
+  if (bi < 0) return fail(MACE_E_NONFINITE, "no candidate configuration ran to a finite residual");
+  *best = opts;
+  best->sv_size = table[bi].sv_size;
+  best->rows_per_agent = table[bi].rows_per_agent;
+  if (best_ms_per_iter) *best_ms_per_iter = table[bi].ms_per_iter;
+  if (results)
+    for (int i = 0; i < std::min((int)table.size(), (int)max_results); ++i) results[i] = table[i];
+  if (n_results) *n_results = (int)table.size();
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = TuneEntry{best->sv_size, best->rows_per_agent, table[bi].ms_per_iter, table};
+  return MACE_OK;
+}

@@ -486,14 +486,15 @@ Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P) {
 }
 
 // Concurrent super-voxels per agent: enough 16-lane rows in total (about
-// 4096, i.e. 1024 waves) to keep every CU busy, but at most a quarter of the
-// SVs of one colour (updating a whole colour at once is block Jacobi, which
-// loses stability on small images).
+// 8192, two waves per SIMD) to keep every CU busy, but at most half of the SVs
+// of one colour -- a quarter on small images (fewer than 256 SVs per colour),
+// where updating most of a colour at once (block Jacobi) loses stability.
 int default_rows_per_agent(const mace_system* s) {
   if (s->rows_per_agent > 0) return s->rows_per_agent;
   const int per_colour = (s->n_sv + 3) / 4;
-  const int P = (4096 + s->N - 1) / s->N;
-  return std::max(1, std::min(P, per_colour / 4));
+  const int P = (8192 + s->N - 1) / s->N;
+  const int cap = per_colour >= 256 ? per_colour / 2 : per_colour / 4;
+  return std::max(1, std::min(P, cap));
 }
 }  // namespace mace
 
@@ -560,6 +561,14 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
   if (!geom || !col_ptr || !row_idx || !val) return fail(MACE_E_ARG, "NULL argument");
   if (geom->nx <= 0 || geom->ny <= 0 || geom->n_views <= 0 || geom->n_channels < 2)
     return fail(MACE_E_ARG, "bad geometry (need sizes > 0 and >= 2 channels)");
+  if (opts && opts->sv_size == -1) {
+    // autotuned S and rows per agent (cached per geometry for the process)
+    mace_opts tuned{};
+    int rc = mace_autotune(geom, col_ptr, row_idx, val, n_agents, view_to_agent, opts, 6, &tuned,
+                           nullptr, nullptr, 0, nullptr);
+    if (rc) return rc;
+    return mace_load_system(geom, col_ptr, row_idx, val, n_agents, view_to_agent, &tuned, out);
+  }
   if ((int64_t)geom->nx * geom->ny > (1LL << 30)) return fail(MACE_E_ARG, "image too large");
   if ((int64_t)geom->n_views * geom->n_channels >= (1LL << 31)) return fail(MACE_E_ARG, "sinogram too large");
   if (n_agents <= 0) return fail(MACE_E_ARG, "n_agents must be > 0");
@@ -573,7 +582,7 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
   if (opts) {
     if (opts->precision != 0 && opts->precision != 1) return fail(MACE_E_ARG, "precision must be 0 or 1");
     if (opts->sv_size != 0 && opts->sv_size != 4 && opts->sv_size != 8)
-      return fail(MACE_E_ARG, "sv_size must be 0 (default 4), 4 or 8");
+      return fail(MACE_E_ARG, "sv_size must be -1 (autotune), 0 (automatic), 4 or 8");
     if (opts->rows_per_agent < 0) return fail(MACE_E_ARG, "rows_per_agent must be >= 0");
     if (opts->fp32_tail_iters < 0) return fail(MACE_E_ARG, "fp32_tail_iters must be >= 0");
     s->precision = opts->precision;
@@ -661,6 +670,17 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
 extern "C" void mace_free_system(mace_system* s) { delete s; }
 
 extern "C" int64_t mace_system_bytes(const mace_system* s) { return s ? s->matrix_bytes : 0; }
+
+extern "C" int mace_get_config(const mace_system* s, mace_opts* out) {
+  if (!s || !out) return fail(MACE_E_ARG, "NULL argument");
+  *out = mace_opts{};
+  out->precision = s->precision;
+  out->sv_size = s->S;
+  out->rows_per_agent = default_rows_per_agent(s);
+  out->fp32_tail_iters = s->fp32_tail;
+  out->refresh_every = s->refresh_every;
+  return MACE_OK;
+}
 
 extern "C" int mace_set_relaxation(mace_system* s, double relax) {
   if (!s) return fail(MACE_E_ARG, "NULL system");
