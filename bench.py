@@ -90,6 +90,207 @@ def cpu_baseline(g, cp, row, val, scan, va, w8, sigma, budget_s=20.0):
                       f"({upd} agent-voxel updates, {dt:.1f} s)"}
 
 
+def _common(metric, value, unit, steps, warmup, ms, dtype, config, higher=True):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def bench_slices(args, m, mi, torch):
+    """64 independent 512x512 slices (own phantoms) sharing one system matrix:
+    all slices advance together through mace_solve_batch_dev (one round of
+    launches per Mann iteration for every slice) versus the same slices solved
+    one at a time with mace_solve_dev.  A step = all slices, 60 iterations."""
+    w8 = mi.WORKLOADS["slices512"]
+    g = w8.geom
+    ns = args.slices
+    log(f"slices: {ns} slices of 512x512; matrix")
+    cp, row, val = mi.system_matrix(g)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w8.n_agents)
+    del cp, row, val
+    prior = m.make_prior(w8.prior_kind, w8.sigma_x, w8.p, w8.q, w8.T)
+    dev = torch.device("cuda:0")
+    ys, ls, xs = [], [], []
+    for i in range(ns):
+        sc = mi.scan(g, w8.seed + i)
+        ys.append(torch.from_numpy(sc.y).to(dev))
+        ls.append(torch.from_numpy(sc.lam).to(dev))
+        xs.append(torch.empty(g.n, dtype=torch.float32, device=dev))
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    yp = [t.data_ptr() for t in ys]
+    lp = [t.data_ptr() for t in ls]
+    xp = [t.data_ptr() for t in xs]
+
+    def batched():
+        return sysm.solve_batch_dev(yp, lp, prior, w8.rho, args.sigma, args.iters, xp, stream_ptr=sp)
+
+    def one_by_one():
+        return [sysm.solve_dev(yp[i], lp[i], prior, w8.rho, args.sigma, args.iters, xp[i],
+                               stream_ptr=sp) for i in range(ns)]
+
+    log("slices: warm-up")
+    for _ in range(args.warmup):
+        batched()
+    one_by_one()
+    torch.cuda.synchronize()
+    x1 = torch.stack(xs).cpu().numpy()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info_b = batched()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    xb = torch.stack(xs).cpu().numpy()
+    t0 = time.perf_counter()
+    info_s = one_by_one()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    diff = float(np.sqrt(((xb - x1) ** 2).sum() / (x1 ** 2).sum()))
+    upd = ns * args.iters * w8.n_agents * g.n
+    out = _common("slices/s (64 x 512x512 slices sharing A, 60 Mann iterations each)",
+                  ns / tb, "slices/s", args.steps, args.warmup, tb * 1e3, "f32",
+                  {"workload": f"slices512: {ns} slices 512x512, 720 views, 736 channels, "
+                               "16 agents, q-GGMRF p=2 q=1.2 T=1 sigma_x=0.01, rho=0.8",
+                   "mann_iters": args.iters, "sigma": args.sigma, "batched": True})
+    out.update({"voxel_updates_per_s": upd / tb,
+                "one_at_a_time_slices_per_s": ns / ts,
+                "speedup_vs_one_at_a_time": ts / tb,
+                "mean_residual_batched": float(np.mean([i.residual for i in info_b])),
+                "mean_residual_one_at_a_time": float(np.mean([i.residual for i in info_s])),
+                "nrmse_batched_vs_one_at_a_time": diff})
+    return out
+
+
+SERVE_SIZES = (("serve256", 2e-4), ("scan512", 1e-4), ("scan1024", 5e-5))
+
+
+def bench_serve(args, m, mi, torch):
+    """Reconstruction service: Poisson arrivals (rate --rate) of scans drawn
+    uniformly from 256^2/360 views/8 agents, 512^2/720/16 and 1024^2/1440/32,
+    each with its own phantom, q-GGMRF prior, stopping at r_k < 1e-4.  The
+    server admits them as memory allows and batches all scans in flight; the
+    latency of a scan runs from its arrival to its result."""
+    import threading
+    rng = np.random.default_rng(2024)
+    systems, pars = [], []
+    for name, sigma in SERVE_SIZES:
+        w = mi.WORKLOADS[name]
+        g = w.geom
+        log(f"serve: loading {name}")
+        cp, row, val = mi.system_matrix(g)
+        systems.append(m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents))
+        del cp, row, val
+        pars.append((w, sigma))
+    kinds = rng.integers(0, len(systems), args.scans)
+    gaps = rng.exponential(1.0 / args.rate, args.scans)
+    log("serve: generating scans")
+    scans = [mi.scan(pars[k][0].geom, 5000 + i) for i, k in enumerate(kinds)]
+    srv = m.Server(systems, hbm_budget_bytes=64 << 30)
+    tickets = [None] * args.scans
+    t_sub = [0.0] * args.scans
+
+    def producer():
+        t_next = time.perf_counter()
+        for i, k in enumerate(kinds):
+            t_next += gaps[i]
+            dt = t_next - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            w, sigma = pars[k]
+            prior = m.make_prior(w.prior_kind, w.sigma_x, w.p, w.q, w.T)
+            t_sub[i] = time.perf_counter()
+            tickets[i] = srv.submit(int(k), scans[i].y, scans[i].lam, prior, w.rho, sigma, 1e-4, 3000)
+
+    log("serve: arrivals")
+    t0 = time.perf_counter()
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    lat, iters, ok = [], [], 0
+    for i, k in enumerate(kinds):
+        x, info, l = srv.wait(tickets[i], systems[k].n)
+        lat.append(l)
+        iters.append(info.iters)
+        ok += info.status == m.MACE_OK
+    t_end = time.perf_counter()
+    st = srv.stats()
+    srv.close()
+    span = t_end - t0
+    by = {}
+    for name_i, (name, _) in enumerate(SERVE_SIZES):
+        li = [lat[i] for i in range(args.scans) if kinds[i] == name_i]
+        it = [iters[i] for i in range(args.scans) if kinds[i] == name_i]
+        if li:
+            by[name] = {"scans": len(li), "p50_ms": float(np.percentile(li, 50) * 1e3),
+                        "p99_ms": float(np.percentile(li, 99) * 1e3),
+                        "mean_iters": float(np.mean(it))}
+    out = _common("scans/s served (Poisson arrivals, mixed sizes, stop at r < 1e-4)",
+                  args.scans / span, "scans/s", args.scans, 0, span / args.scans * 1e3, "f32",
+                  {"workload": f"serve: {args.scans} Poisson arrivals at {args.rate}/s, uniform "
+                               "over 256^2/360 views/8 agents, 512^2/720/16, 1024^2/1440/32; "
+                               "q-GGMRF p=2 q=1.2 T=1 sigma_x=0.01, rho=0.8, tol 1e-4",
+                   "sigma": {n: sg for n, sg in SERVE_SIZES}})
+    out.update({"latency_p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "offered_rate": args.rate, "converged": ok, "by_size": by,
+                "max_in_flight": st["max_in_flight"], "peak_state_bytes": st["peak_bytes"]})
+    return out
+
+
+def bench_fp16(args, m, mi, torch):
+    """1024x1024, 1440 views, 1472 channels, 32 agents, q-GGMRF: system
+    matrix values in FP16 (per agent-pixel FP32 scale) with the last 5 Mann
+    iterations on FP32 values, against the all-FP32 path, same scan and
+    schedule.  A step = one scan, 60 Mann iterations."""
+    w = mi.WORKLOADS["scan1024"]
+    g = w.geom
+    sigma = 5e-5
+    log("fp16: matrix")
+    cp, row, val = mi.system_matrix(g)
+    sc = mi.scan(g, w.seed)
+    prior = m.make_prior(w.prior_kind, w.sigma_x, w.p, w.q, w.T)
+    dev = torch.device("cuda:0")
+    y = torch.from_numpy(sc.y).to(dev)
+    lam = torch.from_numpy(sc.lam).to(dev)
+    x = torch.empty(g.n, dtype=torch.float32, device=dev)
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    res = {}
+    for prec, tail in ((0, 0), (1, 5), (1, 0)):
+        log(f"fp16: loading precision {prec}, FP32 tail {tail}")
+        sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents,
+                        precision=prec, fp32_tail_iters=tail)
+        sysm.set_relaxation(0.5)
+        for _ in range(args.warmup):
+            sysm.solve_dev(y.data_ptr(), lam.data_ptr(), prior, w.rho, sigma, args.iters,
+                           x.data_ptr(), stream_ptr=sp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            info = sysm.solve_dev(y.data_ptr(), lam.data_ptr(), prior, w.rho, sigma, args.iters,
+                                  x.data_ptr(), stream_ptr=sp)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[(prec, tail)] = (dt, x.cpu().numpy().copy(), info.residual, sysm.matrix_bytes)
+        sysm.close()
+    res[0], res[1], r16 = res[(0, 0)], res[(1, 5)], res[(1, 0)]
+    x32, x16 = res[0][1], res[1][1]
+    nrmse = float(np.linalg.norm(x16.astype(np.float64) - x32) / np.linalg.norm(x32))
+    nrmse_pure = float(np.linalg.norm(r16[1].astype(np.float64) - x32) / np.linalg.norm(x32))
+    upd = args.iters * w.n_agents * g.n
+    out = _common("voxel-updates/s, 1024x1024 FP16 matrix values (+5 FP32 iterations)",
+                  upd / res[1][0], "voxel-updates/s", args.steps, args.warmup, res[1][0] * 1e3,
+                  "f16->f32",
+                  {"workload": "scan1024: 1024x1024, 1440 views, 1472 channels, 32 agents, "
+                               "q-GGMRF p=2 q=1.2 T=1 sigma_x=0.01, rho=0.8",
+                   "mann_iters": args.iters, "sigma": sigma, "fp32_tail_iters": 5})
+    out.update({"fp32_voxel_updates_per_s": upd / res[0][0],
+                "fp16_only_voxel_updates_per_s": upd / r16[0],
+                "matrix_bytes_fp16_only": r16[3], "nrmse_fp16_only_vs_fp32": nrmse_pure,
+                "matrix_bytes_fp16": res[1][3], "matrix_bytes_fp32": res[0][3],
+                "nrmse_fp16_vs_fp32": nrmse,
+                "residual_fp16": res[1][2], "residual_fp32": res[0][2]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +304,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--mode", default="scan", choices=("scan", "slices", "serve", "fp16"),
+                    help="scan: the headline one-scan benchmark (default); slices: 64 "
+                         "512x512 slices sharing one matrix, batched vs one at a time; "
+                         "serve: Poisson arrivals of mixed-size scans through the server; "
+                         "fp16: 1024x1024 FP16 matrix values vs FP32")
+    ap.add_argument("--scans", type=int, default=30, help="serve: number of arrivals")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--slices", type=int, default=64, help="slices: batch size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -128,6 +337,10 @@ def main():
     import paper_1911_09278_amd as m
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.mode != "scan":
+        out = {"slices": bench_slices, "serve": bench_serve, "fp16": bench_fp16}[args.mode](args, m, mi, torch)
+        print(json.dumps(out), flush=True)
+        return
     w8 = mi.WORKLOADS["scan512"]
     g = w8.geom
     log("generating system matrix and scan")

@@ -35,10 +35,11 @@ struct SlotDesc {
   float* w;           // [N][n] Mann state
   float* wbar;        // [n] mean of w (updated by the epilogue)
   float* th2;         // [N][n] theta2 = sum_r A_rs^2 Lambda_r
-  double* part;       // [N * n_sv][4] FP64 residual partials per task
+  double* part;       // [N * n_sv][4] FP64 residual partials per task, then
+                      // the epilogue's per-block sums
   double* resid;      // [resid_cap] residual trace
   double* last;       // latest residual (one double)
-  int* counter;       // Mann iterations done
+  int* counter;       // [0] Mann iterations done, [1] epilogue ticket (0 between launches)
   int resid_cap;
   int active;         // 0: the slot's tasks and epilogue are skipped
 };
@@ -82,6 +83,8 @@ hipError_t launch_sv_s8f16(const SvArgs& a, int mode, int slots, int grid, size_
 // Launchers (defined in mace_kernels.hip).
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
 size_t sv_lds_bytes(int bmax, int S, int kpad);
+// Doubles the epilogue needs after a slot's task partials.
+size_t epilogue_scratch_doubles();
 hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int nparts,
                            hipStream_t st);
 hipError_t launch_gather_rows(float* dst, const float* src, const int* row_src, int64_t count,

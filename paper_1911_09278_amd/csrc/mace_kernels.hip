@@ -21,9 +21,43 @@ hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds,
 
 // ---------------- consensus / residual epilogue ----------------
 
-// For every active slot (blockIdx.y): wbar[s] = mean_i w[i][s]; block x = 0
-// also sums the slot's per-task residual partials in a fixed order and stores
-// r_k = sqrt(num) / sqrt(den > 0 ? den : ||X||^2) at the slot's iteration k.
+// For every active slot (blockIdx.y): wbar[s] = mean_i w[i][s], and the
+// slot's residual r_k = sqrt(num) / sqrt(den > 0 ? den : ||X||^2) from the
+// per-task FP64 partials.  The partials are summed in a fixed order whatever
+// the timing: each of the first kEpiRedBlocks blocks sums a fixed chunk and
+// stores its sums after the task partials; the one of those that arrives
+// last (ticket in counter[1]) adds the block sums in block order, stores r_k
+// at iteration k = counter[0] and resets the ticket.
+constexpr int kEpiBlocks = 1024;    // at most this many blocks per slot
+constexpr int kEpiRedBlocks = 64;   // of which this many sum the residual partials
+
+__device__ __forceinline__ double load_l2(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ void block_sum3(double s0, double s1, double s2, double* out) {
+  __shared__ double red[3][256];
+  const int tid = threadIdx.x;
+  red[0][tid] = s0;
+  red[1][tid] = s1;
+  red[2][tid] = s2;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      red[0][tid] += red[0][tid + h];
+      red[1][tid] += red[1][tid + h];
+      red[2][tid] += red[2][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+    out[2] = red[2][0];
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restrict__ slots, int N,
                                                        int n, int nparts) {
   const SlotDesc d = slots[blockIdx.y];
@@ -34,34 +68,47 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
     for (int i = 0; i < N; ++i) m += d.w[(size_t)i * n + s];
     d.wbar[s] = m / (float)N;
   }
-  if (blockIdx.x == 0) {
-    __shared__ double red[3][256];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int p = tid; p < nparts; p += 256) {
-      s0 += d.part[(size_t)p * 4 + 0];
-      s1 += d.part[(size_t)p * 4 + 1];
-      s2 += d.part[(size_t)p * 4 + 2];
-    }
-    red[0][tid] = s0;
-    red[1][tid] = s1;
-    red[2][tid] = s2;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (tid < h) {
-        red[0][tid] += red[0][tid + h];
-        red[1][tid] += red[1][tid + h];
-        red[2][tid] += red[2][tid + h];
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      const int k = *d.counter;
-      const double den = red[1][0] > 0.0 ? red[1][0] : red[2][0];
-      const double r = den > 0.0 ? sqrt(red[0][0]) / sqrt(den) : 0.0;
-      if (k < d.resid_cap) d.resid[k] = r;
-      *d.last = r;
-      *d.counter = k + 1;
-    }
+  // this block's fixed chunk of the task partials (the first kEpiRedBlocks
+  // blocks only, so that few blocks take a ticket)
+  const int nb = min((int)gridDim.x, kEpiRedBlocks);
+  if ((int)blockIdx.x >= nb) return;
+  const int chunk = (nparts + nb - 1) / nb;
+  const int p0 = blockIdx.x * chunk, p1 = min(nparts, p0 + chunk);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int p = p0 + tid; p < p1; p += 256) {
+    s0 += d.part[(size_t)p * 4 + 0];
+    s1 += d.part[(size_t)p * 4 + 1];
+    s2 += d.part[(size_t)p * 4 + 2];
+  }
+  __shared__ double bs[3];
+  __shared__ int last;
+  block_sum3(s0, s1, s2, bs);
+  double* bpart = d.part + (size_t)nparts * 4;
+  if (tid == 0) {
+    bpart[blockIdx.x * 4 + 0] = bs[0];
+    bpart[blockIdx.x * 4 + 1] = bs[1];
+    bpart[blockIdx.x * 4 + 2] = bs[2];
+    __threadfence();
+    last = atomicAdd(&d.counter[1], 1) == nb - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  s0 = s1 = s2 = 0.0;
+  for (int b = tid; b < nb; b += 256) {
+    s0 += load_l2(bpart + b * 4 + 0);
+    s1 += load_l2(bpart + b * 4 + 1);
+    s2 += load_l2(bpart + b * 4 + 2);
+  }
+  block_sum3(s0, s1, s2, bs);
+  if (tid == 0) {
+    const int k = d.counter[0];
+    const double den = bs[1] > 0.0 ? bs[1] : bs[2];
+    const double r = den > 0.0 ? sqrt(bs[0]) / sqrt(den) : 0.0;
+    if (k < d.resid_cap) d.resid[k] = r;
+    *d.last = r;
+    d.counter[0] = k + 1;
+    d.counter[1] = 0;
   }
 }
 
@@ -69,10 +116,12 @@ hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int
                            hipStream_t st) {
   if (n_slots <= 0) return hipSuccess;
   int gx = (n + 255) / 256;
-  if (gx > 1024) gx = 1024;
+  if (gx > kEpiBlocks) gx = kEpiBlocks;
   hipLaunchKernelGGL(epilogue_kernel, dim3(gx, n_slots), dim3(256), 0, st, slots, N, n, nparts);
   return hipGetLastError();
 }
+
+size_t epilogue_scratch_doubles() { return (size_t)kEpiRedBlocks * 4; }
 
 // ---------------- small helpers ----------------
 

@@ -20,7 +20,8 @@ namespace mace {
 
 int64_t slot_bytes(const mace_system* s, int resid_cap) {
   const int64_t nimg = (int64_t)s->N * s->n, nrow = (int64_t)s->N * s->estride;
-  return 4 * (3 * nrow + 3 * nimg + s->n) + 8 * ((int64_t)s->N * s->n_sv * 4 + std::max(1, resid_cap)) + 4;
+  return 4 * (3 * nrow + 3 * nimg + s->n) +
+         8 * ((int64_t)s->N * s->n_sv * 4 + (int64_t)epilogue_scratch_doubles() + std::max(1, resid_cap)) + 8;
 }
 
 int ensure_slot(mace_system* s, Batch& b, int idx, int resid_cap) {
@@ -37,8 +38,9 @@ int ensure_slot(mace_system* s, Batch& b, int idx, int resid_cap) {
     HIP_OK(q.w.alloc(nimg));
     HIP_OK(q.th2.alloc(nimg));
     HIP_OK(q.wbar.alloc(s->n));
-    HIP_OK(q.part.alloc((size_t)s->N * s->n_sv * 4));
-    HIP_OK(q.counter.alloc(1));
+    HIP_OK(q.part.alloc((size_t)s->N * s->n_sv * 4 + epilogue_scratch_doubles()));
+    HIP_OK(q.counter.alloc(2));
+    HIP_OK(hipMemset(q.counter.p, 0, 2 * sizeof(int)));  // the epilogue ticket starts at 0
   }
   const int cap = std::max(1, resid_cap);
   if (q.resid_cap < cap) {
@@ -156,7 +158,7 @@ int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam
   else
     HIP_OK(launch_fill(q.w.p, 0.f, nimg, st));
   HIP_OK(launch_broadcast_mean(q.w.p, q.wbar.p, q.X.p, s->N, s->n, st));
-  HIP_OK(hipMemsetAsync(q.counter.p, 0, sizeof(int), st));
+  HIP_OK(hipMemsetAsync(q.counter.p, 0, 2 * sizeof(int), st));
   HIP_OK(hipMemsetAsync(b.lastres.p + i, 0, sizeof(double), st));
   int rc = write_slot(s, b, i, 1, st);
   if (rc) return rc;
