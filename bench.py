@@ -70,7 +70,7 @@ def measured_traffic():
     return float(m_t.group(1))
 
 
-def cpu_baseline(g, cp, row, val, scan, va, w8, sigma, budget_s=20.0):
+def cpu_baseline(g, cp, row, val, scan, va, w8, sigma, budget_s=50.0):
     """The FP64 oracle (as it stands) on a bounded sample: whole Mann iterations
     of the same scan, timed on this host."""
     import oracle
