@@ -21,6 +21,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 VALU ops stay off (hardware note in the design doc)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # the sweep's per-pixel loop over a super-voxel must unroll fully
+         # (records in registers), beyond LLVM's default size limit
+         "-mllvm", "-pragma-unroll-threshold=1000000",
          "-I", os.path.join(ROOT, "include")]
 
 
