@@ -210,3 +210,49 @@ def test_full_size_scan512(m):
         ei = O.error_sinogram(X[i].astype(np.float64), agent=int(i))
         r = np.where(va[np.arange(g.n_rows) // g.n_channels] == i)[0]
         assert np.abs(e[r] - ei[r]).max() <= 1e-4 * np.abs(s.y).max()
+
+
+def test_full_size_scan1024_fp16(m):
+    """1024x1024, 1440 views, 1472 channels, 32 agents (the FP16 workload).
+    Sequential schedule, FP32 values: one iteration matches the oracle element
+    by element.  Benchmark schedule: the FP16 path stays within 1e-3 of the
+    FP32 path (before any FP32 refinement), and its error sinogram equals
+    y - A X_i up to the FP16 rounding of A."""
+    w = mi.WORKLOADS["scan1024"]
+    g = w.geom
+    print("building 1024x1024 system matrix", flush=True)
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, w.seed)
+    va = mi.interleaved_partition(g.n_views, w.n_agents)
+    sigma = 5e-5
+    prior = m.make_prior(1, w.sigma_x, 2.0, w.q, w.T)
+    seq = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents,
+                   rows_per_agent=1)
+    seq.set_relaxation(0.5)
+    x1, _ = seq.solve(s.y, s.lam, prior, w.rho, sigma, 1)
+    order = seq.visit_order()
+    seq.close()
+    print("oracle setup and iteration", flush=True)
+    O = oracle.Oracle(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, s.y, s.lam, va, 1,
+                      w.sigma_x, 2.0, w.q, w.T)
+    ref = O.mace_solve(w.rho, sigma, 1, order=order, relax=0.5)
+    assert np.abs(x1 - ref["x"]).max() <= 5e-5 * np.abs(ref["x"]).max()
+    print("FP16 vs FP32, benchmark schedule", flush=True)
+    xs = {}
+    for prec in (0, 1):
+        sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents,
+                        precision=prec)
+        sysm.set_relaxation(0.5)
+        xs[prec], info = sysm.solve(s.y, s.lam, prior, w.rho, sigma, 3)
+        assert np.isfinite(info.residual)
+        if prec == 1:
+            _, X = sysm.state()
+            e = sysm.error_sinogram()
+            i = 5
+            ei = O.error_sinogram(X[i].astype(np.float64), agent=i)
+            r = np.where(va[np.arange(g.n_rows) // g.n_channels] == i)[0]
+            assert np.abs(e[r] - ei[r]).max() <= 2e-3 * np.abs(s.y).max()
+        sysm.close()
+    err = _nrmse(xs[1], xs[0].astype(np.float64))
+    print("fp16 vs fp32 nrmse", err, flush=True)
+    assert err <= 1e-3
