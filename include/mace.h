@@ -82,11 +82,12 @@ typedef struct {
                              -1 = autotuned with rows_per_agent (see
                              mace_autotune) */
   int32_t rows_per_agent; /* concurrent super-voxels per agent; 0 = automatic
-                             (about 8192 in total over the agents, at most
-                             half of one colour's super-voxels -- a quarter
-                             below 256 per colour); 1 = sequential (one
-                             super-voxel of an agent at a time: the visiting
-                             order of mace_visit_order) */
+                             (about 8192 rows in total over the agents, and
+                             at least a quarter of one colour's super-voxels,
+                             but at most half of them -- a quarter below 256
+                             per colour); 1 = sequential (one super-voxel of
+                             an agent at a time: the visiting order of
+                             mace_visit_order) */
   int32_t fp32_tail_iters;/* with precision 1: last iterations in FP32 A */
   int64_t hbm_budget_bytes; /* 0 = no limit */
   int32_t refresh_every;  /* recompute e = y - A X_i every this many Mann
@@ -152,7 +153,8 @@ int mace_solve_dev(mace_system* sys, const float* y, const float* lambda,
  * With rows_per_agent = 1 every scan follows exactly the iterates mace_solve
  * computes for it alone.  With the automatic rows_per_agent the concurrent
  * super-voxels per (scan, agent) are divided by n_scans, so the total
- * concurrency stays about the same; the scans then reach the same fixed
+ * concurrency stays about the same and the scans walk the super-voxels in
+ * step (sharing the matrix reads); the scans then reach the same fixed
  * points by different iterates.  Returns the worst status over the scans.
  */
 int mace_solve_batch(mace_system* sys, int32_t n_scans, const float* const* y,

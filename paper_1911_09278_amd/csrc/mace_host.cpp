@@ -396,9 +396,12 @@ static void build_schedule(const mace_system* s, int n_slots, int only_agent, in
   };
   const int nxcd = 8;
   std::vector<std::vector<RowId>> xrows(nxcd);
-  for (int sl = 0; sl < n_slots; ++sl)
-    for (size_t i = 0; i < agents.size(); ++i)
-      for (int r = 0; r < P; ++r) xrows[agents[i] % nxcd].push_back({sl, agents[i], r});
+  // rank-major: the rows that run at the same time (consecutive workgroups)
+  // hold the same rank of every slot and agent, so the slots of a batch
+  // walk the super-voxels in step and share the matrix records in L2
+  for (int r = 0; r < P; ++r)
+    for (int sl = 0; sl < n_slots; ++sl)
+      for (size_t i = 0; i < agents.size(); ++i) xrows[agents[i] % nxcd].push_back({sl, agents[i], r});
   int wg_per_xcd = 0, used = 0;
   for (int x = 0; x < nxcd; ++x) {
     wg_per_xcd = std::max<int>(wg_per_xcd, (int)((xrows[x].size() + kRowsPerBlock - 1) / kRowsPerBlock));
@@ -486,13 +489,16 @@ Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P) {
 }
 
 // Concurrent super-voxels per agent: enough 16-lane rows in total (about
-// 8192, two waves per SIMD) to keep every CU busy, but at most half of the SVs
-// of one colour -- a quarter on small images (fewer than 256 SVs per colour),
+// 8192, two waves per SIMD) to keep every CU busy, and enough that a row
+// runs at most kMaxTasksPerRow super-voxels per phase (short workgroups let
+// the launches of other streams in between), but at most half of the SVs of
+// one colour -- a quarter on small images (fewer than 256 SVs per colour),
 // where updating most of a colour at once (block Jacobi) loses stability.
+constexpr int kMaxTasksPerRow = 4;
 int default_rows_per_agent(const mace_system* s) {
   if (s->rows_per_agent > 0) return s->rows_per_agent;
   const int per_colour = (s->n_sv + 3) / 4;
-  const int P = (8192 + s->N - 1) / s->N;
+  const int P = std::max((8192 + s->N - 1) / s->N, (per_colour + kMaxTasksPerRow - 1) / kMaxTasksPerRow);
   const int cap = per_colour >= 256 ? per_colour / 2 : per_colour / 4;
   return std::max(1, std::min(P, cap));
 }

@@ -149,6 +149,7 @@ int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, co
                   bool theta2, hipStream_t st);
 int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, const SvArgs& a,
                   int sweeps, int P, hipStream_t st);
-// Rows per (scan, agent) when n scans run together.
-int batch_rows_per_agent(const mace_system* s, int n);
+// Rows per (scan, agent) when n scans run together (share_gpu: other
+// streams run launches beside them).
+int batch_rows_per_agent(const mace_system* s, int n, bool share_gpu);
 }  // namespace mace

@@ -166,7 +166,7 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
     int n_occ = 0;
     for (int i = 0; i < (int)g->req.size(); ++i)
       if (g->req[i]) n_occ = i + 1;
-    const int P = batch_rows_per_agent(s, act);
+    const int P = batch_rows_per_agent(s, act, true);
     Schedule* sch = get_schedule(s, n_occ, -1, P);
     if (!sch) return fail(MACE_E_HIP, "schedule upload failed");
     SvArgs a;

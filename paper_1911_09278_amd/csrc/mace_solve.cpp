@@ -224,9 +224,15 @@ int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, co
   return MACE_OK;
 }
 
-int batch_rows_per_agent(const mace_system* s, int n) {
+// Rows per (scan, agent) for n scans in flight.  A batch that owns the GPU
+// divides the automatic value by n: about the same number of rows in total,
+// each row sweeping many super-voxels with all scans in step (the matrix
+// records are shared in L2).  Scans that share the GPU with other streams
+// (the server) keep the single-scan value: more, shorter workgroups, which
+// lets the other streams' launches in between.
+int batch_rows_per_agent(const mace_system* s, int n, bool share_gpu) {
   const int P = default_rows_per_agent(s);
-  if (s->rows_per_agent > 0 || n <= 1) return P;
+  if (share_gpu || s->rows_per_agent > 0 || n <= 1) return P;
   return std::max(1, P / n);
 }
 
@@ -259,7 +265,7 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
   Batch& b = s->batch;
   hipStream_t st = s->stream;
   if (user) HIP_OK(hipStreamSynchronize(user));  // the caller's inputs are ready
-  const int P = batch_rows_per_agent(s, n);
+  const int P = batch_rows_per_agent(s, n, false);
   Schedule* sch = get_schedule(s, n, -1, P);
   if (!sch) return fail(MACE_E_HIP, "schedule upload failed");
   for (int i = 0; i < n; ++i) {
