@@ -146,3 +146,30 @@ def test_server_rejects_bad_arguments_without_a_device():
     assert L.mace_server_stats(None, None) == m.MACE_E_ARG
     L.mace_server_destroy(None)
     assert L.mace_scan_bytes(None) == 0
+
+
+def test_batch_and_autotune_reject_bad_arguments_without_a_device():
+    import ctypes
+    import paper_1911_09278_amd as m
+    L = m._lib
+    pr = m.make_prior(0, 0.01)
+    info = (m.Info * 2)()
+    assert L.mace_solve_batch(None, 2, None, None, ctypes.byref(pr), 0.8, 0.01, 1, 10, 0.0,
+                              None, info) == m.MACE_E_ARG
+    assert L.mace_solve_batch_dev(None, 2, None, None, ctypes.byref(pr), 0.8, 0.01, 1, 10, 0.0,
+                                  None, info, None) == m.MACE_E_ARG
+    best = m.Opts()
+    g = m.Geom(8, 8, 4, 8)
+    assert L.mace_autotune(None, None, None, None, 2, None, None, 4, ctypes.byref(best), None,
+                           None, 0, None) == m.MACE_E_ARG
+    cp = np.zeros(65, dtype=np.int64)
+    row = np.zeros(1, dtype=np.int32)
+    val = np.zeros(1, dtype=np.float32)
+    assert L.mace_autotune(ctypes.byref(g), cp.ctypes.data, row.ctypes.data, val.ctypes.data, 0,
+                           None, None, 4, ctypes.byref(best), None, None, 0,
+                           None) == m.MACE_E_ARG
+    assert L.mace_autotune(ctypes.byref(g), cp.ctypes.data, row.ctypes.data, val.ctypes.data, 2,
+                           None, None, 0, ctypes.byref(best), None, None, 0,
+                           None) == m.MACE_E_ARG
+    assert L.mace_get_config(None, ctypes.byref(best)) == m.MACE_E_ARG
+    assert "NULL" in m.last_error()
