@@ -80,6 +80,25 @@ def test_sequential_trajectory_matches_oracle(m, case):
     assert abs(info.residual - ref["resid"][-1]) <= 1e-3 * ref["resid"][-1] + 1e-7
 
 
+def test_sequential_two_sweeps_and_warm_start_match_oracle(m):
+    """Two ICD passes per partial update (Algorithm 1 with sweeps = 2) from a
+    nonzero w^0: the trajectory still matches the oracle."""
+    g = mi.Geometry(32, 32, 64, 48)
+    N, sx, sigma = 4, 0.002, 0.002
+    (cp, row, val), s, va, O = _setup(g, 77, N, 1, sx, 1.2)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, rows_per_agent=1)
+    prior = m.make_prior(1, sx, 2.0, 1.2, 1.0)
+    rng = np.random.default_rng(5)
+    w0 = rng.uniform(0.0, 0.03, N * g.n).astype(np.float32)
+    x, info = sysm.solve(s.y, s.lam, prior, 0.8, sigma, 3, sweeps=2, w_init=w0)
+    order = sysm.visit_order()
+    ref = O.mace_solve(0.8, sigma, 3, sweeps=2, w_init=w0.astype(np.float64), order=order,
+                       mode=oracle.MODE_SURROGATE)
+    scale = np.abs(ref["x"]).max()
+    assert info.iters == 3 and info.equits == 6
+    assert np.abs(x - ref["x"]).max() <= 5e-5 * scale, np.abs(x - ref["x"]).max() / scale
+
+
 def test_prox_single_pass_matches_oracle(m):
     g = mi.Geometry(32, 32, 90, 48)
     N = 3
