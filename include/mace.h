@@ -115,6 +115,9 @@ typedef struct {
  *   agent k mod n_agents); every agent must own at least one view and at most
  *   128 views.
  * The matrix is copied and repacked on the device; *out receives the handle.
+ * A super-voxel's band (its channels in every view of the agent) is staged in
+ * LDS: workgroups hold 16 rows, or 8 or 4 when a band is too large for 16
+ * (many views per agent); MACE_E_ARG if even 4 rows do not fit 160 KiB.
  * Errors: MACE_E_ARG, MACE_E_MATRIX, MACE_E_PARTITION, MACE_E_NOMEM, MACE_E_HIP.
  */
 int mace_load_system(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
@@ -259,7 +262,8 @@ int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, const int32_t* 
  * device tables and the super-voxel schedules in host memory and checks every
  * index the kernels form from them (band rows, record rows, task ids, LDS
  * size), without using a device.  *lds_bytes (optional) receives the LDS a
- * workgroup of the main kernel needs.  Same error codes as mace_load_system.
+ * workgroup of the main kernel needs (for the rows per workgroup chosen: 16,
+ * 8 or 4).  Same error codes as mace_load_system.
  */
 int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
                       const float* val, int32_t n_agents, const int32_t* view_to_agent,

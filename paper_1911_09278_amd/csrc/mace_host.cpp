@@ -370,16 +370,26 @@ static int check_pack(const mace_system* s, const HostPack& hp) {
   return MACE_OK;
 }
 
+// Rows per workgroup of the sweep kernel: 16 (two workgroups per CU at
+// 79 KB each for the 45-view workloads), fewer when a row's band, halo and
+// scratch would not fit 16 to the 160 KiB of LDS (many views per agent).
+static int pick_rows_per_block(mace_system* s) {
+  s->rpb = sv_rows_per_block(s->bmax, s->S, s->kpad);
+  if (s->rpb == 0)
+    return fail(MACE_E_ARG,
+                "a super-voxel band of %d rows needs more than 40 KiB of LDS per row; %s", s->bmax,
+                s->S > 4 ? "use sv_size 4" : "use more agents (fewer views per agent)");
+  return MACE_OK;
+}
+
 // ---------------------------------------------------------------- schedules
-// Rows of 16 lanes are grouped 16 to a workgroup; workgroups are dispatched
-// round-robin over the 8 XCDs, so the rows serving one agent are placed in
-// workgroups of one XCD where possible (its e/Lambda then live in one L2).
 struct HostSchedule {
   int grid = 0, R = 0, T[4] = {0, 0, 0, 0};
   std::vector<int> tab[4];
 };
 
-// Rows of 16 lanes are grouped 16 to a workgroup; workgroups are dispatched
+// Rows of 16 lanes are grouped s->rpb to a workgroup (16 unless a row's LDS
+// is too large for that); workgroups are dispatched
 // round-robin over the 8 XCDs. The rows serving agent a (of every slot) are
 // placed in workgroups of XCD a mod 8, so the agent's sinogram blocks and its
 // matrix records stay in one L2; all slots walk the SVs in the same order, so
@@ -404,27 +414,27 @@ static void build_schedule(const mace_system* s, int n_slots, int only_agent, in
       for (size_t i = 0; i < agents.size(); ++i) xrows[agents[i] % nxcd].push_back({sl, agents[i], r});
   int wg_per_xcd = 0, used = 0;
   for (int x = 0; x < nxcd; ++x) {
-    wg_per_xcd = std::max<int>(wg_per_xcd, (int)((xrows[x].size() + kRowsPerBlock - 1) / kRowsPerBlock));
+    wg_per_xcd = std::max<int>(wg_per_xcd, (int)((xrows[x].size() + s->rpb - 1) / s->rpb));
     used += !xrows[x].empty();
   }
   std::vector<RowId> row_of;
   if (used == nxcd) {
     hs.grid = wg_per_xcd * nxcd;
-    row_of.assign((size_t)hs.grid * kRowsPerBlock, {-1, -1, -1});
+    row_of.assign((size_t)hs.grid * s->rpb, {-1, -1, -1});
     for (int x = 0; x < nxcd; ++x)
       for (size_t q = 0; q < xrows[x].size(); ++q) {
-        const int u = (int)(q / kRowsPerBlock), j = (int)(q % kRowsPerBlock);
-        row_of[(size_t)(u * nxcd + x) * kRowsPerBlock + j] = xrows[x][q];
+        const int u = (int)(q / s->rpb), j = (int)(q % s->rpb);
+        row_of[(size_t)(u * nxcd + x) * s->rpb + j] = xrows[x][q];
       }
   } else {
     // some XCDs would stay idle: pack the rows densely instead
     std::vector<RowId> all;
     for (int x = 0; x < nxcd; ++x) all.insert(all.end(), xrows[x].begin(), xrows[x].end());
-    hs.grid = (int)((all.size() + kRowsPerBlock - 1) / kRowsPerBlock);
-    row_of.assign((size_t)hs.grid * kRowsPerBlock, {-1, -1, -1});
+    hs.grid = (int)((all.size() + s->rpb - 1) / s->rpb);
+    row_of.assign((size_t)hs.grid * s->rpb, {-1, -1, -1});
     for (size_t q = 0; q < all.size(); ++q) row_of[q] = all[q];
   }
-  hs.R = hs.grid * kRowsPerBlock;
+  hs.R = hs.grid * s->rpb;
   for (int c = 0; c < 4; ++c) {
     const auto& L = s->colour_svs[c];
     const int T = (int)((L.size() + P - 1) / P);
@@ -517,6 +527,7 @@ void mace::fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, doub
   a.kpad = s->kpad;
   a.bmax = s->bmax;
   a.wmax = s->wmax;
+  a.rpb = s->rpb;
   a.sv_pix0 = s->d_sv_pix0.p;
   a.aval = s->aval.p;
   a.hval = s->hval.p;
@@ -609,12 +620,11 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
     if (rc) return rc;
     rc = check_pack(s.get(), hp);
     if (rc) return rc;
+    rc = pick_rows_per_block(s.get());
+    if (rc) return rc;
     rc = upload_pack(s.get(), hp);
     if (rc) return rc;
   }
-  if (sv_lds_bytes(s->bmax, s->S, s->kpad) > 160 * 1024)
-    return fail(MACE_E_ARG, "super-voxel band needs %zu bytes of LDS per workgroup; use a smaller sv_size",
-                sv_lds_bytes(s->bmax, s->S, s->kpad));
   HIP_OK(hipGetDevice(&s->device));
   HIP_OK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
   *out = s.release();
@@ -656,6 +666,8 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
   if (rc) return rc;
   rc = check_pack(&s, hp);
   if (rc) return rc;
+  rc = pick_rows_per_block(&s);
+  if (rc) return rc;
   const int P = default_rows_per_agent(&s);
   for (int only = -1; only < s.N; ++only) {
     for (int PP : {1, P}) {
@@ -669,7 +681,6 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
     if (only >= 2) break;
   }
   if (lds_bytes) *lds_bytes = (int64_t)sv_lds_bytes(s.bmax, s.S, s.kpad);
-  if (sv_lds_bytes(s.bmax, s.S, s.kpad) > 160 * 1024) return fail(MACE_E_ARG, "LDS per workgroup exceeds 160 KiB");
   return MACE_OK;
 }
 

@@ -6,11 +6,12 @@
 
 namespace mace {
 
-// One row of 16 lanes works on one super-voxel; a 256-thread workgroup holds
-// 4 waves x 4 rows.
+// One row of 16 lanes works on one super-voxel; a workgroup holds up to
+// 4 waves x 4 rows (fewer when a row's LDS is large: 16, 8 or 4 rows).
 constexpr int kRowLanes = 16;
-constexpr int kRowsPerBlock = 16;
-constexpr int kBlockThreads = 256;
+constexpr int kMaxRowsPerBlock = 16;
+constexpr int kBlockThreads = kMaxRowsPerBlock * kRowLanes;
+constexpr size_t kMaxLdsBytes = 160 * 1024;
 constexpr int kMaxSlots = 8;  // views per agent <= 16 * kMaxSlots
 
 // Band of one (agent, super-voxel, agent-local view): channels
@@ -72,6 +73,7 @@ struct SvArgs {
   int mann;             // apply the reflection + Mann update at the end
   int fp16;             // read the FP16 records
   int strict;           // one SV of an agent at a time: stage e after the previous flush
+  int rpb;              // rows per workgroup (16, 8 or 4); the block has rpb * 16 threads
 };
 
 // Per-variant sweep launchers (mace_sweep_*.hip).
@@ -82,6 +84,9 @@ hipError_t launch_sv_s8f16(const SvArgs& a, int mode, int slots, int grid, size_
 
 // Launchers (defined in mace_kernels.hip).
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
+// Rows per workgroup: the most of 16, 8, 4 whose LDS fits in 160 KiB (0 if
+// none does), and the LDS bytes of such a workgroup.
+int sv_rows_per_block(int bmax, int S, int kpad);
 size_t sv_lds_bytes(int bmax, int S, int kpad);
 // Doubles the epilogue needs after a slot's task partials.
 size_t epilogue_scratch_doubles();

@@ -8,7 +8,16 @@
 
 namespace mace {
 
-size_t sv_lds_bytes(int bmax, int S, int kpad) { return kRowsPerBlock * row_lds_bytes(bmax, S, kpad); }
+int sv_rows_per_block(int bmax, int S, int kpad) {
+  for (int rpb = kMaxRowsPerBlock; rpb >= 4; rpb /= 2)
+    if ((size_t)rpb * row_lds_bytes(bmax, S, kpad) <= kMaxLdsBytes) return rpb;
+  return 0;
+}
+
+size_t sv_lds_bytes(int bmax, int S, int kpad) {
+  const int rpb = sv_rows_per_block(bmax, S, kpad);
+  return (size_t)(rpb > 0 ? rpb : 4) * row_lds_bytes(bmax, S, kpad);
+}
 
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st) {
   if (grid <= 0) return hipSuccess;

@@ -99,6 +99,7 @@ struct mace_system {
   int Kmax = 0, slots = 0, kpad = 0;
   int S = 0, gx = 0, gy = 0, n_sv = 0;
   int bmax = 0;
+  int rpb = 0;  // rows per workgroup of the sweep kernel (16, 8 or 4)
   int wmax = 0;
   int precision = 0;
   int rows_per_agent = 0;

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
   const int lane64 = threadIdx.x & 63;
   const int lr = lane64 & 15;
   const int rib = ((threadIdx.x >> 6) << 2) | (lane64 >> 4);  // row in block
-  const int row = blockIdx.x * kRowsPerBlock + rib;
+  const int row = blockIdx.x * a.rpb + rib;
   const size_t per_row = row_lds_bytes(a.bmax, S, KP);
   char* base = smem + rib * per_row;
   float2* band = reinterpret_cast<float2*>(base);
@@ -538,11 +538,11 @@ inline hipError_t launch_mode(const SvArgs& a, int slots, int grid, size_t lds, 
     if (!attr_set.load(std::memory_order_acquire)) {                                     \
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel<SLV, MODE, SV, F16V>), \
                                          hipFuncAttributeMaxDynamicSharedMemorySize,     \
-                                         160 * 1024);                                    \
+                                         (int)kMaxLdsBytes);                              \
       if (e != hipSuccess) return e;                                                     \
       attr_set.store(true, std::memory_order_release);                                   \
     }                                                                                    \
-    hipLaunchKernelGGL((sv_kernel<SLV, MODE, SV, F16V>), dim3(grid), dim3(kBlockThreads), lds, st, a); \
+    hipLaunchKernelGGL((sv_kernel<SLV, MODE, SV, F16V>), dim3(grid), dim3(a.rpb * kRowLanes), lds, st, a); \
     break;                                                                               \
   }
     MACE_CASE(1)

@@ -105,10 +105,14 @@ LAYOUT_CASES = [
     (mi.Geometry(32, 32, 90, 48), 3, 4), (mi.Geometry(40, 40, 96, 60), 4, 4),
     (mi.Geometry(48, 48, 96, 72), 4, 4), (mi.Geometry(64, 64, 90, 96), 4, 4),
     (mi.Geometry(33, 17, 45, 40), 3, 8), (mi.Geometry(16, 16, 24, 24), 8, 4),
+    # 75 to 128 views per agent: bands too large for 16 rows per workgroup
+    (mi.Geometry(24, 24, 150, 40), 2, 8), (mi.Geometry(26, 26, 200, 40), 2, 4),
+    (mi.Geometry(20, 20, 128, 32), 1, 8),
 ]
 
 
-@pytest.mark.parametrize("case", LAYOUT_CASES, ids=lambda c: f"{c[0].nx}x{c[0].ny}_N{c[1]}_S{c[2]}")
+@pytest.mark.parametrize("case", LAYOUT_CASES,
+                         ids=lambda c: f"{c[0].nx}x{c[0].ny}v{c[0].n_views}_N{c[1]}_S{c[2]}")
 def test_device_layout_indices_in_bounds(case):
     import paper_1911_09278_amd as m
     g, N, S = case

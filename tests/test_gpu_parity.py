@@ -52,11 +52,16 @@ SEQ_CASES = [
     (mi.Geometry(24, 24, 100, 40), 2, 1, 0.002, 1.2, 0.002, 8, 3, 1.0),  # 50 views: 4 slots, S = 8
     (mi.Geometry(20, 20, 30, 32), 1, 1, 0.003, 1.5, 0.003, 4, 3, 1.0),   # single agent
     (mi.Geometry(36, 36, 90, 56), 2, 1, 0.01, 1.2, 2e-4, 4, 5, 0.5),     # under-relaxed
+    # more than 64 views per agent: the staged e lives in LDS, and large
+    # bands take 8 or 4 rows per workgroup
+    (mi.Geometry(24, 24, 150, 40), 2, 1, 0.002, 1.2, 0.002, 8, 3, 1.0),  # 75 views: 5 slots, 8 rows
+    (mi.Geometry(26, 26, 200, 40), 2, 0, 0.002, 2.0, 0.002, 4, 3, 1.0),  # 100 views: 7 slots, 16 rows
+    (mi.Geometry(20, 20, 128, 32), 1, 1, 0.003, 1.5, 0.003, 8, 3, 1.0),  # 128 views: 8 slots (most)
 ]
 
 
 @pytest.mark.parametrize("case", SEQ_CASES,
-                         ids=lambda c: f"{c[0].nx}x{c[0].ny}_N{c[1]}_k{c[2]}_S{c[6]}_g{c[8]}")
+                         ids=lambda c: f"{c[0].nx}x{c[0].ny}v{c[0].n_views}_N{c[1]}_k{c[2]}_S{c[6]}_g{c[8]}")
 def test_sequential_trajectory_matches_oracle(m, case):
     g, N, kind, sx, q, sigma, S, iters, relax = case
     (cp, row, val), s, va, O = _setup(g, 101 + g.nx, N, kind, sx, q)
