@@ -315,7 +315,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+              "(the library runs every agent on one GPU; sharding agents over GPUs is "
+              "designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -3,6 +3,7 @@ exports every function include/mace.h declares, and rejects malformed input
 before touching the device."""
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -177,3 +178,12 @@ def test_batch_and_autotune_reject_bad_arguments_without_a_device():
                            None) == m.MACE_E_ARG
     assert L.mace_get_config(None, ctypes.byref(best)) == m.MACE_E_ARG
     assert "NULL" in m.last_error()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU and says so for --gpus N > 1 (exit 2)."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
