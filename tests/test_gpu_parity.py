@@ -140,6 +140,28 @@ def test_concurrent_fixed_point_is_the_map(m):
     assert _nrmse(x, xmap) <= 1e-4, _nrmse(x, xmap)
 
 
+def test_concurrent_many_views_fixed_point_is_the_map(m):
+    """75 views per agent with 8x8 super-voxels: bands too large for 16 rows
+    per workgroup, so the concurrent schedule runs 8-row workgroups; its
+    fixed point is still the MAP (dense Cholesky, quadratic prior)."""
+    from tests import dense_ref as dr
+    g = mi.Geometry(64, 64, 150, 96)
+    N, sx, sigma = 2, 0.001, 3e-4
+    (cp, row, val), s, va, O = _setup(g, 29, N, 0, sx)
+    lds = m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=8)
+    assert 80 * 1024 < lds <= 160 * 1024  # more than 16 rows of it would not fit
+    A = dr.dense_A(g, cp, row, val)
+    xmap = dr.map_quadratic(A, s.lam.astype(np.float64), s.y.astype(np.float64),
+                            dr.laplacian(g.nx, g.ny), sx)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=8)
+    assert sysm.config["rows_per_agent"] > 1
+    sysm.set_relaxation(0.5)
+    x, info = sysm.solve(s.y, s.lam, m.make_prior(0, sx), 0.8, sigma, 6000, tol=1e-6)
+    print("iters", info.iters, "resid", info.residual, flush=True)
+    assert info.status == m.MACE_OK
+    assert _nrmse(x, xmap) <= 1e-4, _nrmse(x, xmap)
+
+
 def test_concurrent_qggmrf_fixed_point(m):
     g = mi.Geometry(40, 40, 96, 60)
     N, sx, sigma = 4, 0.0015, 0.001
