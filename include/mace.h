@@ -88,7 +88,12 @@ typedef struct {
                              per colour); 1 = sequential (one super-voxel of
                              an agent at a time: the visiting order of
                              mace_visit_order) */
-  int32_t fp32_tail_iters;/* with precision 1: last iterations in FP32 A */
+  int32_t fp32_tail_iters;/* with precision 1: the last this many of the
+                             max_iters iterations of mace_solve /
+                             mace_solve_batch run with FP32 A (after an
+                             e-refresh with FP32 A); a scan that meets tol
+                             earlier stops in FP16, and the server, whose
+                             scans stop on tol, runs FP16 throughout */
   int64_t hbm_budget_bytes; /* 0 = no limit */
   int32_t refresh_every;  /* recompute e = y - A X_i every this many Mann
                              iterations to stop FP32 drift (0 = never) */
