@@ -53,6 +53,33 @@ def test_sequential_batch_follows_single_scans(m):
         assert info.iters == iters and info.status == m.MACE_OK
 
 
+def test_sequential_fp16_batch_with_fp32_tail_follows_single_scans(m):
+    """FP16 matrix values with a two-iteration FP32 tail: every scan of a
+    batch follows its own single-scan solve, through the precision switch
+    (e-refresh with FP32 A, theta2 rebuilt)."""
+    g = mi.Geometry(32, 32, 64, 48)
+    N, sx, sigma, iters = 4, 0.002, 0.002, 5
+    cp, row, val = mi.system_matrix(g)
+    scans = [mi.scan(g, seed) for seed in (14, 15, 16)]
+    print("sequential FP16 batch of 3 with FP32 tail, 32x32 N=4", flush=True)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=4,
+                    rows_per_agent=1, precision=1, fp32_tail_iters=2)
+    prior = m.make_prior(1, sx, 2.0, 1.2, 1.0)
+    xs, infos = sysm.solve_batch([s.y for s in scans], [s.lam for s in scans], prior, 0.8,
+                                 sigma, iters)
+    fp32 = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=4,
+                    rows_per_agent=1)
+    for s, x, info in zip(scans, xs, infos):
+        alone, _ = sysm.solve(s.y, s.lam, prior, 0.8, sigma, iters)
+        assert np.abs(x - alone).max() <= 1e-6 * np.abs(alone).max()
+        assert info.iters == iters and info.status == m.MACE_OK
+        # FP16 values for 3 iterations, then FP32: close to the FP32 path
+        x32, _ = fp32.solve(s.y, s.lam, prior, 0.8, sigma, iters)
+        err = np.abs(x - x32).max() / np.abs(x32).max()
+        print("max rel. difference to FP32", err, flush=True)
+        assert 0 < err <= 2e-3
+
+
 def test_concurrent_batch_per_scan_stopping(m):
     from tests import dense_ref as dr
     g = mi.Geometry(32, 32, 64, 48)
