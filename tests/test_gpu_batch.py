@@ -8,6 +8,8 @@
    different iterations; an all-zero scan is done after one iteration.
 3. The captured iteration graph and the eager launches (timing mode) give the
    same iterates.
+4. FP16 matrix values with an FP32 tail: each scan of a batch follows its own
+   single-scan solve through the precision switch.
 """
 import numpy as np
 import pytest
