@@ -8,6 +8,9 @@
    budget fails with MACE_E_NOMEM while the others complete.
 3. Scans with different solver parameters run in separate groups of one
    system and still match their alone results.
+4. A system with FP16 matrix values served beside an FP32 one: its scans
+   match their alone results, and stay within the FP16 bar (1e-3) of the
+   MAP.
 """
 import threading
 import time
@@ -141,3 +144,32 @@ def test_groups_with_different_parameters(m):
     assert i1.status == m.MACE_OK and i2.status == m.MACE_OK
     assert _nrmse(x1, x1a) <= 1e-4
     assert _nrmse(x2, x2a) <= 1e-4
+
+
+def test_fp16_system_served_beside_fp32(m):
+    from tests import dense_ref as dr
+    cp, row, val = mi.system_matrix(GA)
+    s16 = m.System(GA.nx, GA.ny, GA.n_views, GA.n_channels, cp, row, val, 4, precision=1)
+    s32 = m.System(GA.nx, GA.ny, GA.n_views, GA.n_channels, cp, row, val, 4)
+    systems = [s16, s32]
+    prior = m.make_prior(0, SX)
+    jobs = [(0, mi.scan(GA, 61)), (1, mi.scan(GA, 62)), (0, mi.scan(GA, 63))]
+    alone = []
+    for k, s in jobs:
+        x, info = systems[k].solve(s.y, s.lam, prior, 0.8, SIGMA, 4000, tol=TOL)
+        assert info.status == m.MACE_OK
+        alone.append(x)
+    srv = m.Server(systems)
+    try:
+        tickets = [srv.submit(k, s.y, s.lam, prior, 0.8, SIGMA, TOL, 4000) for k, s in jobs]
+        out = [srv.wait(t, GA.n) for t in tickets]
+    finally:
+        srv.close()
+    A = dr.dense_A(GA, cp, row, val)
+    L = dr.laplacian(GA.nx, GA.ny)
+    for (k, s), (x, info, lat), xa in zip(jobs, out, alone):
+        xmap = dr.map_quadratic(A, s.lam.astype(np.float64), s.y.astype(np.float64), L, SX)
+        print("fp16" if k == 0 else "fp32", info.iters, _nrmse(x, xa), _nrmse(x, xmap), flush=True)
+        assert info.status == m.MACE_OK and info.residual < TOL
+        assert _nrmse(x, xa) <= 1e-4
+        assert _nrmse(x, xmap) <= (1e-3 if k == 0 else 1e-4)
