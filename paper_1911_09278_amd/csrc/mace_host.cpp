@@ -116,7 +116,7 @@ struct HostPack {
   std::vector<float2> aval;
   std::vector<__half2> hval;
   std::vector<float> hscale;
-  std::vector<uint16_t> aoff;
+  std::vector<uint32_t> adel;  // packed row deltas, kpad / 8 words per record
   std::vector<BandEnt> band;
   std::vector<int> brows;
   std::vector<int> row_src;
@@ -148,8 +148,8 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
     h_hval.resize(nrec);
     h_hscale.resize((size_t)N * n);
   }
-  std::vector<uint16_t>& h_aoff = hp.aoff;
-  h_aoff.resize(nrec);
+  std::vector<uint32_t>& h_adel = hp.adel;
+  h_adel.assign(nrec / 8, 0u);
   std::vector<BandEnt>& h_band = hp.band;
   h_band.resize((size_t)N * s->n_sv * kpad);
   std::vector<int>& h_brows = hp.brows;
@@ -165,7 +165,6 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
     th.emplace_back([&, t] {
       std::vector<Foot> foot;         // [npix][n_views]
       std::vector<int> cmin(s->n_views), cmax(s->n_views);
-      std::vector<int> lrow(s->n_views);
       for (int sv = t; sv < s->n_sv && !err; sv += nth) {
         const int sy = sv / s->gx, sx = sv % s->gx;
         const int y0 = sy * S, x0 = sx * S;
@@ -230,10 +229,12 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
               }
             }
             cmin[k] = lo;
-            lrow[k] = b.lds_row;
             h_band[asv * kpad + kl] = b;
           }
-          for (int kl = K; kl < kpad; ++kl) h_band[asv * kpad + kl] = BandEnt{0, 0, 0};
+          // views that miss the SV, and padding views, point at the dummy rows
+          for (int kl = 0; kl < K; ++kl)
+            if (h_band[asv * kpad + kl].width == 0) h_band[asv * kpad + kl].lds_row = (uint16_t)B;
+          for (int kl = K; kl < kpad; ++kl) h_band[asv * kpad + kl] = BandEnt{0, (uint16_t)B, 0};
           if (B + 2 > 65535) {
             err = 3;
             return;
@@ -254,19 +255,20 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
             for (int kl = 0; kl < kpad; ++kl) {
               const size_t idx = rec * kpad + kl;
               float a0 = 0.f, a1 = 0.f;
-              int off = B;  // dummy rows
+              uint32_t del = 0;  // a view the pixel misses: row 0 of its band, a0 = a1 = 0
               if (kl < K) {
                 const int k = vw[kl];
                 const Foot& f = foot[(size_t)j * s->n_views + k];
                 if (f.any) {
                   a0 = f.a0;
                   a1 = f.a1;
-                  off = lrow[k] + (f.d0 - cmin[k]);
+                  del = (uint32_t)(f.d0 - cmin[k]);
                 }
               }
               if (!h_aval.empty()) h_aval[idx] = make_float2(a0, a1);
               if (!h_hval.empty()) h_hval[idx] = __floats2half2_rn(a0 / scale, a1 / scale);
-              h_aoff[idx] = (uint16_t)off;
+              // slot kl = 16 s + l: word 2 s + l / 8, nibble l mod 8
+              h_adel[rec * (kpad / 8) + (kl / 16) * 2 + (kl % 16) / 8] |= (del & 15u) << (4 * (kl % 8));
             }
           }
         }
@@ -305,7 +307,7 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
 }
 
 static int upload_pack(mace_system* s, const HostPack& hp) {
-  HIP_OK(s->aoff.upload(hp.aoff.data(), hp.aoff.size()));
+  HIP_OK(s->adel.upload(hp.adel.data(), hp.adel.size()));
   if (!hp.aval.empty()) HIP_OK(s->aval.upload(hp.aval.data(), hp.aval.size()));
   if (!hp.hval.empty()) {
     HIP_OK(s->hval.upload(hp.hval.data(), hp.hval.size()));
@@ -316,7 +318,7 @@ static int upload_pack(mace_system* s, const HostPack& hp) {
   HIP_OK(s->d_sv_pix0.upload(s->sv_pix0.data(), s->sv_pix0.size()));
   HIP_OK(s->row_src.upload(hp.row_src.data(), hp.row_src.size()));
   s->matrix_bytes = (int64_t)(s->aval.bytes() + s->hval.bytes() + s->hscale.bytes() +
-                              s->aoff.bytes() + s->band.bytes() + s->band_rows.bytes());
+                              s->adel.bytes() + s->band.bytes() + s->band_rows.bytes());
   return MACE_OK;
 }
 
@@ -333,8 +335,10 @@ static int check_pack(const mace_system* s, const HostPack& hp) {
       for (int kl = 0; kl < kpad; ++kl) {
         const BandEnt& b = hp.band[asv * kpad + kl];
         if (b.width == 0) {
-          // the kernel reads entry gstart of an empty band
+          // the kernel reads entry gstart of an empty band, and its records
+          // address the dummy rows B, B + 1
           if (b.gstart != 0) return fail(MACE_E_MATRIX, "check: empty band with gstart %u", b.gstart);
+          if (b.lds_row != B) return fail(MACE_E_MATRIX, "check: empty band off the dummy rows");
           continue;
         }
         if (kl >= K) return fail(MACE_E_MATRIX, "check: band entry on a padding view");
@@ -351,12 +355,13 @@ static int check_pack(const mace_system* s, const HostPack& hp) {
       for (int j = 0; j < npix; ++j) {
         const size_t rec = (size_t)a * s->n + s->sv_pix0[sv] + j;
         for (int kl = 0; kl < kpad; ++kl) {
-          const int off = hp.aoff[rec * kpad + kl];
-          if (off > B) return fail(MACE_E_MATRIX, "check: record row %d beyond band (%d)", off, B);
-          if (kl < K && off < B) {
-            const BandEnt& b = hp.band[asv * kpad + kl];
-            if (off < b.lds_row || off + 1 >= b.lds_row + b.width)
-              return fail(MACE_E_MATRIX, "check: record row outside its view's band");
+          // the kernel reads and writes band rows lds_row + del and the next one
+          const int del = (int)((hp.adel[rec * (kpad / 8) + (kl / 16) * 2 + (kl % 16) / 8] >> (4 * (kl % 8))) & 15u);
+          const BandEnt& b = hp.band[asv * kpad + kl];
+          if (b.width == 0) {
+            if (b.lds_row != B || del != 0) return fail(MACE_E_MATRIX, "check: empty view not on the dummy rows");
+          } else if (del + 1 >= b.width) {
+            return fail(MACE_E_MATRIX, "check: record row %d outside its view's band (%d rows)", del, b.width);
           }
         }
       }
@@ -533,7 +538,7 @@ void mace::fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, doub
   a.hval = s->hval.p;
   a.hscale = s->hscale.p;
   a.fp16 = fp16 ? 1 : 0;
-  a.aoff = s->aoff.p;
+  a.adel = s->adel.p;
   a.band = s->band.p;
   a.band_rows = s->band_rows.p;
   a.estride = s->estride;

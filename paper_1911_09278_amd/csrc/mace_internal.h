@@ -18,7 +18,7 @@ constexpr int kMaxSlots = 8;  // views per agent <= 16 * kMaxSlots
 // [cmin, cmin + width) of that view, staged in LDS from row lds_row on.
 struct BandEnt {
   uint32_t gstart;   // index of (view, cmin) in the agent's sinogram block
-  uint16_t lds_row;  // first LDS row of the band
+  uint16_t lds_row;  // first LDS row of the band (the dummy rows B when width is 0)
   uint16_t width;    // channels in the band (0: the view misses the SV)
 };
 
@@ -57,7 +57,7 @@ struct SvArgs {
   const float2* aval;   // FP32 records: (a0, a1) per (agent, pixel, view slot)
   const __half2* hval;  // FP16 records (precision 1), scaled by hscale
   const float* hscale;  // [N * n] per (agent, pixel) scale of the FP16 values
-  const uint16_t* aoff; // LDS row of channel d0 per (agent, pixel, view slot)
+  const uint32_t* adel; // row of d0 in its view's band, 4 bits per (agent, pixel, view slot)
   const BandEnt* band;  // [(agent * n_sv + sv) * kpad + view]
   const int* band_rows; // [agent * n_sv + sv] rows B of the band (dummy rows at B, B+1)
   int64_t estride;      // per-agent stride of e / lam blocks

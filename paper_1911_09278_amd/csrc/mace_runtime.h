@@ -114,7 +114,7 @@ struct mace_system {
   mace::DevBuf<float2> aval;
   mace::DevBuf<__half2> hval;
   mace::DevBuf<float> hscale;
-  mace::DevBuf<uint16_t> aoff;
+  mace::DevBuf<uint32_t> adel;
   mace::DevBuf<mace::BandEnt> band;
   mace::DevBuf<int> band_rows;
   mace::DevBuf<int> d_sv_pix0;

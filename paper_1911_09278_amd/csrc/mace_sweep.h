@@ -78,15 +78,22 @@ __device__ __forceinline__ float2 load_vals(const SvArgs& a, size_t idx, float s
 }
 
 // Record of one pixel for the lane's view slots: (a0, a1) on channels d0,
-// d0 + 1 and the LDS row of d0.
+// d0 + 1, and the row of d0 within its view's band (4 bits; 0 for a view the
+// pixel misses, whose a0 = a1 = 0).  The row deltas of a pixel are packed
+// eight to a 32-bit word: slot s * 16 + lr sits in word 2 s + lr / 8, bits
+// 4 (lr mod 8) .. 4 (lr mod 8) + 3.
 constexpr int kPrefetch = 3;
 constexpr int kFlushGroup = 16;  // views per group in the band write-back
 
 template <int SL>
 struct Rec {
   float2 val[SL];
-  int off[SL];
+  int off[SL];  // row delta within the view's band
 };
+
+__device__ __forceinline__ int row_delta(uint32_t word, int lr) {
+  return (int)__builtin_amdgcn_ubfe(word, 4u * (uint32_t)(lr & 7), 4u);
+}
 
 template <int SL, bool F16>
 __device__ __forceinline__ void load_rec(const SvArgs& a, size_t rec, int lr, Rec<SL>& r) {
@@ -96,7 +103,7 @@ __device__ __forceinline__ void load_rec(const SvArgs& a, size_t rec, int lr, Re
   for (int s = 0; s < SL; ++s) {
     const size_t idx = rec * (SL * kRowLanes) + s * kRowLanes + lr;
     r.val[s] = load_vals<F16>(a, idx, scale);
-    r.off[s] = a.aoff[idx];
+    r.off[s] = row_delta(a.adel[rec * (SL * 2) + s * 2 + (lr >> 3)], lr);
   }
 }
 
@@ -104,7 +111,7 @@ __device__ __forceinline__ void load_rec(const SvArgs& a, size_t rec, int lr, Re
 // of the SV's first pixel): the offsets are compile-time constants.
 template <int SL, bool F16>
 __device__ __forceinline__ void load_rec_at(const float2* vb, const __half2* hb, const float* sb,
-                                            const uint16_t* ob, int j, Rec<SL>& r) {
+                                            const uint32_t* db, int lr, int j, Rec<SL>& r) {
   constexpr int KP = SL * kRowLanes;
   float scale = 1.0f;
   if constexpr (F16) scale = sb[j];
@@ -116,7 +123,7 @@ __device__ __forceinline__ void load_rec_at(const float2* vb, const __half2* hb,
     } else {
       r.val[s] = vb[j * KP + s * kRowLanes];
     }
-    r.off[s] = ob[j * KP + s * kRowLanes];
+    r.off[s] = row_delta(db[j * (SL * 2) + s * 2], lr);
   }
 }
 
@@ -363,15 +370,23 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
 
     // ---- 2. pixel loop: records prefetched kPrefetch pixels ahead ----
     const size_t rec0 = (size_t)agent * a.n + pix0;
+    // first LDS row of each of the lane's views in this task's band (the
+    // dummy rows of the task for a view that misses the super-voxel)
+    int lrw[SL];
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) lrw[sl] = cur.cb[sl].lds_row;
     auto update = [&](const Rec<SL>& cur, int j, int pi, int pj) {
       const int cidx = (pi + 1) * HS + pj + 1;
+      int o[SL];
+#pragma unroll
+      for (int s2 = 0; s2 < SL; ++s2) o[s2] = lrw[s2] + cur.off[s2];
       if (MODE == kSweep) {
         // every LDS read of this pixel first, then the arithmetic
         float2 p0[SL], p1[SL];
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2) {
-          p0[s2] = band[cur.off[s2]];
-          p1[s2] = band[cur.off[s2] + 1];
+          p0[s2] = band[o[s2]];
+          p1[s2] = band[o[s2] + 1];
         }
         const float zs = halo[cidx];
         const float nbv = halo[cidx + noff];
@@ -391,15 +406,15 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
         const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(tj + H + a.is2);
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2) {
-          band[cur.off[s2]].x = p0[s2].x - cur.val[s2].x * alpha;
-          band[cur.off[s2] + 1].x = p1[s2].x - cur.val[s2].y * alpha;
+          band[o[s2]].x = p0[s2].x - cur.val[s2].x * alpha;
+          band[o[s2] + 1].x = p1[s2].x - cur.val[s2].y * alpha;
         }
         if (lr == 0) halo[cidx] = zs + alpha;
       } else if (MODE == kTheta2) {
         float part = 0.0f;
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2) {
-          const float l0 = band[cur.off[s2]].y, l1 = band[cur.off[s2] + 1].y;
+          const float l0 = band[o[s2]].y, l1 = band[o[s2] + 1].y;
           part += cur.val[s2].x * cur.val[s2].x * l0 + cur.val[s2].y * cur.val[s2].y * l1;
         }
         const float th = row_sum16(part);
@@ -411,8 +426,8 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
         const float xs = halo[cidx];
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2) {
-          band[cur.off[s2]].x -= cur.val[s2].x * xs;
-          band[cur.off[s2] + 1].x -= cur.val[s2].y * xs;
+          band[o[s2]].x -= cur.val[s2].x * xs;
+          band[o[s2] + 1].x -= cur.val[s2].y * xs;
         }
       }
       __builtin_amdgcn_wave_barrier();
@@ -424,14 +439,14 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
       const float2* vb = F16 ? nullptr : a.aval + rb;
       const __half2* hb = F16 ? a.hval + rb : nullptr;
       const float* sb = F16 ? a.hscale + rec0 : nullptr;
-      const uint16_t* ob = a.aoff + rb;
+      const uint32_t* db = a.adel + rec0 * (SL * 2) + (lr >> 3);
       Rec<SL> buf[S * S];
 #pragma unroll
-      for (int q = 0; q < kPrefetch; ++q) load_rec_at<SL, F16>(vb, hb, sb, ob, q, buf[q]);
+      for (int q = 0; q < kPrefetch; ++q) load_rec_at<SL, F16>(vb, hb, sb, db, lr, q, buf[q]);
 #pragma unroll
       for (int j = 0; j < S * S; ++j) {
         if (j + kPrefetch < S * S)
-          load_rec_at<SL, F16>(vb, hb, sb, ob, j + kPrefetch, buf[j + kPrefetch]);
+          load_rec_at<SL, F16>(vb, hb, sb, db, lr, j + kPrefetch, buf[j + kPrefetch]);
         update(buf[j], j, j / S, j % S);
       }
     } else {
