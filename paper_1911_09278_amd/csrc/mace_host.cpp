@@ -30,6 +30,11 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 const std::string& last_error_text() { return g_err; }
+
+std::mutex& capture_mutex() {
+  static std::mutex mu;
+  return mu;
+}
 }  // namespace mace
 
 extern "C" const char* mace_last_error(void) { return g_err.c_str(); }
@@ -140,12 +145,16 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
     for (size_t k = 0; k < s->views[a].size(); ++k) local[s->views[a][k]] = (int)k;
 
   const size_t nrec = (size_t)N * n * kpad;
+  // values at stride Kmax per record, plus a tail pad of one slot group that
+  // the lanes past Kmax of the last record read (and zero)
+  const int kstr = s->Kmax;
+  const size_t nval = (size_t)N * n * kstr + kRowLanes;
   std::vector<float2>& h_aval = hp.aval;
   std::vector<__half2>& h_hval = hp.hval;
   std::vector<float>& h_hscale = hp.hscale;
-  if (s->precision == 0 || s->fp32_tail > 0) h_aval.resize(nrec);
+  if (s->precision == 0 || s->fp32_tail > 0) h_aval.assign(nval, make_float2(0.f, 0.f));
   if (s->precision == 1) {
-    h_hval.resize(nrec);
+    h_hval.assign(nval, __floats2half2_rn(0.f, 0.f));
     h_hscale.resize((size_t)N * n);
   }
   std::vector<uint32_t>& h_adel = hp.adel;
@@ -253,7 +262,7 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
             const float scale = mx > 0.f ? mx : 1.f;
             if (!h_hscale.empty()) h_hscale[rec] = scale;
             for (int kl = 0; kl < kpad; ++kl) {
-              const size_t idx = rec * kpad + kl;
+              const size_t idx = rec * kstr + kl;  // used for kl < kstr only
               float a0 = 0.f, a1 = 0.f;
               uint32_t del = 0;  // a view the pixel misses: row 0 of its band, a0 = a1 = 0
               if (kl < K) {
@@ -265,8 +274,10 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
                   del = (uint32_t)(f.d0 - cmin[k]);
                 }
               }
-              if (!h_aval.empty()) h_aval[idx] = make_float2(a0, a1);
-              if (!h_hval.empty()) h_hval[idx] = __floats2half2_rn(a0 / scale, a1 / scale);
+              if (kl < kstr) {
+                if (!h_aval.empty()) h_aval[idx] = make_float2(a0, a1);
+                if (!h_hval.empty()) h_hval[idx] = __floats2half2_rn(a0 / scale, a1 / scale);
+              }
               // slot kl = 16 s + l: word 2 s + l / 8, nibble l mod 8
               h_adel[rec * (kpad / 8) + (kl / 16) * 2 + (kl % 16) / 8] |= (del & 15u) << (4 * (kl % 8));
             }
@@ -533,6 +544,7 @@ void mace::fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, doub
   a.bmax = s->bmax;
   a.wmax = s->wmax;
   a.rpb = s->rpb;
+  a.kstr = s->Kmax;
   a.sv_pix0 = s->d_sv_pix0.p;
   a.aval = s->aval.p;
   a.hval = s->hval.p;

@@ -54,7 +54,7 @@ struct SvArgs {
   const int* tasks;     // [R][T] task = agent * n_sv + sv, or -1
   int T, R;
   const int* sv_pix0;   // [n_sv + 1] first record of each super-voxel
-  const float2* aval;   // FP32 records: (a0, a1) per (agent, pixel, view slot)
+  const float2* aval;   // FP32 records: (a0, a1) per (agent, pixel, view < kstr)
   const __half2* hval;  // FP16 records (precision 1), scaled by hscale
   const float* hscale;  // [N * n] per (agent, pixel) scale of the FP16 values
   const uint32_t* adel; // row of d0 in its view's band, 4 bits per (agent, pixel, view slot)
@@ -74,6 +74,7 @@ struct SvArgs {
   int fp16;             // read the FP16 records
   int strict;           // one SV of an agent at a time: stage e after the previous flush
   int rpb;              // rows per workgroup (16, 8 or 4); the block has rpb * 16 threads
+  int kstr;             // record values per (agent, pixel): the largest view count of an agent
 };
 
 // Per-variant sweep launchers (mace_sweep_*.hip).

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,11 @@ namespace mace {
 // Records the calling thread's error message and returns code.
 int fail(int code, const char* fmt, ...);
 const std::string& last_error_text();
+
+// Held while a stream captures an iteration graph and around the library's
+// device and pinned-host allocations and frees: in this runtime such a call
+// on one thread can invalidate a capture running on another.
+std::mutex& capture_mutex();
 
 #define HIP_OK(expr)                                                                       \
   do {                                                                                     \
@@ -35,7 +41,10 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { reset(); }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      std::lock_guard<std::mutex> lk(capture_mutex());
+      (void)hipFree(p);
+    }
     p = nullptr;
     count = 0;
   }
@@ -43,6 +52,7 @@ struct DevBuf {
     reset();
     count = n;
     if (n == 0) return hipSuccess;
+    std::lock_guard<std::mutex> lk(capture_mutex());
     return hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
   }
   hipError_t upload(const T* h, size_t n) {
@@ -96,7 +106,7 @@ struct Batch {
 
 struct mace_system {
   int nx = 0, ny = 0, n = 0, n_views = 0, n_ch = 0, N = 0;
-  int Kmax = 0, slots = 0, kpad = 0;
+  int Kmax = 0, slots = 0, kpad = 0;  // record values are stored at stride Kmax
   int S = 0, gx = 0, gy = 0, n_sv = 0;
   int bmax = 0;
   int rpb = 0;  // rows per workgroup of the sweep kernel (16, 8 or 4)
@@ -148,8 +158,10 @@ int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam
                const float* w_init, const SvArgs& base, hipStream_t st);
 int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, const SvArgs& base,
                   bool theta2, hipStream_t st);
+// One Mann iteration; through a captured graph when use_graph (the batch
+// solve), eager launches otherwise (the server's worker threads).
 int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, const SvArgs& a,
-                  int sweeps, int P, hipStream_t st);
+                  int sweeps, int P, hipStream_t st, bool use_graph = true);
 // Rows per (scan, agent) when n scans run together (share_gpu: other
 // streams run launches beside them).
 int batch_rows_per_agent(const mace_system* s, int n, bool share_gpu);

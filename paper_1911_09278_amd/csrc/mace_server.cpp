@@ -137,6 +137,7 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
   for (auto& [g, i] : admitted) {
     Request* r = g->req[i];
     if (!g->hlast) {
+      std::lock_guard<std::mutex> lk(capture_mutex());
       HIP_OK(hipHostMalloc(reinterpret_cast<void**>(&g->hlast), sizeof(double) * kMaxScanSlots,
                            hipHostMallocDefault));
       HIP_OK(hipEventCreateWithFlags(&g->ev, hipEventDisableTiming));
@@ -176,7 +177,8 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
       int rc = refresh_slots(s, g->batch, n_occ, sch, a, false, st);
       if (rc) return rc;
     }
-    int rc = run_iteration(s, g->batch, sch, n_occ, a, g->sweeps, P, st);
+    // eager launches: a worker thread captures no graph (see capture_mutex)
+    int rc = run_iteration(s, g->batch, sch, n_occ, a, g->sweeps, P, st, false);
     if (rc) return rc;
     ++g->ticks;
     HIP_OK(hipMemcpyAsync(g->hlast, g->batch.lastres.p, sizeof(double) * n_occ,

@@ -198,7 +198,8 @@ int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, co
 // given configuration runs eagerly (it also performs the one-time kernel
 // attribute set-up, which stays out of the capture); the second captures.
 int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, const SvArgs& a,
-                  int sweeps, int P, hipStream_t st) {
+                  int sweeps, int P, hipStream_t st, bool use_graph) {
+  if (!use_graph) return enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
   const auto key = std::make_tuple(n_slots, P, sweeps, a.fp16, args_key(a));
   auto it = b.graphs.find(key);
   if (it == b.graphs.end()) {
@@ -207,10 +208,15 @@ int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, co
   }
   if (!it->second) {
     auto ng = std::make_unique<IterGraph>();
-    HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    int rc = enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
     hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(st, &graph);
+    int rc;
+    hipError_t e;
+    {
+      std::lock_guard<std::mutex> lk(capture_mutex());
+      HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
+      e = hipStreamEndCapture(st, &graph);
+    }
     if (rc) {
       if (graph) (void)hipGraphDestroy(graph);
       return rc;
@@ -289,6 +295,7 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
   if (timing && (int)s->ev.size() < 2 * max_iters + 2) {
     for (auto e : s->ev) (void)hipEventDestroy(e);
     s->ev.assign(2 * max_iters + 2, nullptr);
+    std::lock_guard<std::mutex> lk(capture_mutex());
     for (auto& e : s->ev) HIP_OK(hipEventCreate(&e));
   }
   if (timing) HIP_OK(hipEventRecord(s->ev[2 * max_iters], st));

@@ -95,34 +95,44 @@ __device__ __forceinline__ int row_delta(uint32_t word, int lr) {
   return (int)__builtin_amdgcn_ubfe(word, 4u * (uint32_t)(lr & 7), 4u);
 }
 
+// The values of a record are stored for the agents' largest view count
+// kstr (not the padded 16 SL slots); a lane past it reads the next record
+// (or the array's tail pad) and zeroes what it read.
 template <int SL, bool F16>
 __device__ __forceinline__ void load_rec(const SvArgs& a, size_t rec, int lr, Rec<SL>& r) {
   float scale = 1.0f;
   if constexpr (F16) scale = a.hscale[rec];
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
-    const size_t idx = rec * (SL * kRowLanes) + s * kRowLanes + lr;
-    r.val[s] = load_vals<F16>(a, idx, scale);
+    const size_t idx = rec * a.kstr + s * kRowLanes + lr;
+    const float2 v = load_vals<F16>(a, idx, scale);
+    const bool ok = s * kRowLanes + lr < a.kstr;
+    r.val[s] = make_float2(ok ? v.x : 0.0f, ok ? v.y : 0.0f);
     r.off[s] = row_delta(a.adel[rec * (SL * 2) + s * 2 + (lr >> 3)], lr);
   }
 }
 
 // Record j of a super-voxel from per-SV base pointers (the lane's first slot
-// of the SV's first pixel): the offsets are compile-time constants.
+// of the SV's first pixel; values at stride kstr, row deltas at 2 SL words).
+// Only the last slot group can run past kstr: last_ok says whether this
+// lane's slot there is a view.
 template <int SL, bool F16>
 __device__ __forceinline__ void load_rec_at(const float2* vb, const __half2* hb, const float* sb,
-                                            const uint32_t* db, int lr, int j, Rec<SL>& r) {
-  constexpr int KP = SL * kRowLanes;
+                                            const uint32_t* db, int kstr, bool last_ok, int lr,
+                                            int j, Rec<SL>& r) {
   float scale = 1.0f;
   if constexpr (F16) scale = sb[j];
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
+    float2 v;
     if constexpr (F16) {
-      const float2 f = __half22float2(hb[j * KP + s * kRowLanes]);
-      r.val[s] = make_float2(f.x * scale, f.y * scale);
+      const float2 f = __half22float2(hb[(size_t)j * kstr + s * kRowLanes]);
+      v = make_float2(f.x * scale, f.y * scale);
     } else {
-      r.val[s] = vb[j * KP + s * kRowLanes];
+      v = vb[(size_t)j * kstr + s * kRowLanes];
     }
+    if (s == SL - 1) v = make_float2(last_ok ? v.x : 0.0f, last_ok ? v.y : 0.0f);
+    r.val[s] = v;
     r.off[s] = row_delta(db[j * (SL * 2) + s * 2], lr);
   }
 }
@@ -435,18 +445,21 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
     if (npix == S * S) {
       // full super-voxel: straight-line code, every record in its own
       // registers, so each wait covers exactly the record it needs
-      const size_t rb = rec0 * KP + lr;
+      const int kstr = a.kstr;
+      const bool last_ok = (SL - 1) * kRowLanes + lr < kstr;
+      const size_t rb = rec0 * kstr + lr;
       const float2* vb = F16 ? nullptr : a.aval + rb;
       const __half2* hb = F16 ? a.hval + rb : nullptr;
       const float* sb = F16 ? a.hscale + rec0 : nullptr;
       const uint32_t* db = a.adel + rec0 * (SL * 2) + (lr >> 3);
       Rec<SL> buf[S * S];
 #pragma unroll
-      for (int q = 0; q < kPrefetch; ++q) load_rec_at<SL, F16>(vb, hb, sb, db, lr, q, buf[q]);
+      for (int q = 0; q < kPrefetch; ++q)
+        load_rec_at<SL, F16>(vb, hb, sb, db, kstr, last_ok, lr, q, buf[q]);
 #pragma unroll
       for (int j = 0; j < S * S; ++j) {
         if (j + kPrefetch < S * S)
-          load_rec_at<SL, F16>(vb, hb, sb, db, lr, j + kPrefetch, buf[j + kPrefetch]);
+          load_rec_at<SL, F16>(vb, hb, sb, db, kstr, last_ok, lr, j + kPrefetch, buf[j + kPrefetch]);
         update(buf[j], j, j / S, j % S);
       }
     } else {
