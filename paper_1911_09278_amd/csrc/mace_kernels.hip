@@ -73,8 +73,17 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
   if (!d.active) return;
   const int tid = threadIdx.x;
   for (int s = blockIdx.x * blockDim.x + tid; s < n; s += gridDim.x * blockDim.x) {
+    // eight agents' loads in flight before they are added, in agent order
     float m = 0.0f;
-    for (int i = 0; i < N; ++i) m += d.w[(size_t)i * n + s];
+    int i = 0;
+    for (; i + 8 <= N; i += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = d.w[(size_t)(i + u) * n + s];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) m += v[u];
+    }
+    for (; i < N; ++i) m += d.w[(size_t)i * n + s];
     d.wbar[s] = m / (float)N;
   }
   // this block's fixed chunk of the task partials (the first kEpiRedBlocks
