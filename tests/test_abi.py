@@ -187,3 +187,16 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_binding_refuses_to_import_without_the_library(tmp_path):
+    """No fallback: the package raises at import when libmace.so is not built."""
+    import shutil
+    import subprocess
+    pkg = tmp_path / "paper_1911_09278_amd"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_1911_09278_amd", "__init__.py"), pkg / "__init__.py")
+    r = subprocess.run([sys.executable, "-c", "import paper_1911_09278_amd"], cwd=str(tmp_path),
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libmace.so is missing" in r.stderr
