@@ -57,6 +57,7 @@ struct Group {
   double* hlast = nullptr;  // pinned read-back of the slots' residuals
   hipEvent_t ev = nullptr;
   ~Group() {
+    std::lock_guard<std::mutex> lk(capture_mutex());
     if (hlast) (void)hipHostFree(hlast);
     if (ev) (void)hipEventDestroy(ev);
   }
