@@ -41,6 +41,7 @@ extern "C" const char* mace_last_error(void) { return g_err.c_str(); }
 
 mace_system::~mace_system() {
   batch.graphs.clear();
+  std::lock_guard<std::mutex> lk(capture_mutex());
   for (auto e : ev) (void)hipEventDestroy(e);
   if (stream) (void)hipStreamDestroy(stream);
 }
@@ -643,7 +644,10 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
     if (rc) return rc;
   }
   HIP_OK(hipGetDevice(&s->device));
-  HIP_OK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+  {
+    std::lock_guard<std::mutex> lk(capture_mutex());
+    HIP_OK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
+  }
   *out = s.release();
   g_err.clear();
   return MACE_OK;

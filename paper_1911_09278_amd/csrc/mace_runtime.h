@@ -86,6 +86,7 @@ struct IterGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~IterGraph() {
+    std::lock_guard<std::mutex> lk(capture_mutex());
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
   }

@@ -217,13 +217,13 @@ int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, co
       rc = enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
       e = hipStreamEndCapture(st, &graph);
     }
-    if (rc) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc;
-    }
+    ng->graph = graph;  // destroyed with ng on every return below
+    if (rc) return rc;
     HIP_OK(e);
-    ng->graph = graph;
-    HIP_OK(hipGraphInstantiate(&ng->exec, graph, nullptr, nullptr, 0));
+    {
+      std::lock_guard<std::mutex> lk(capture_mutex());
+      HIP_OK(hipGraphInstantiate(&ng->exec, graph, nullptr, nullptr, 0));
+    }
     it->second = std::move(ng);
   }
   HIP_OK(hipGraphLaunch(it->second->exec, st));
@@ -293,9 +293,9 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
     }
   const bool timing = s->timing;
   if (timing && (int)s->ev.size() < 2 * max_iters + 2) {
+    std::lock_guard<std::mutex> lk(capture_mutex());
     for (auto e : s->ev) (void)hipEventDestroy(e);
     s->ev.assign(2 * max_iters + 2, nullptr);
-    std::lock_guard<std::mutex> lk(capture_mutex());
     for (auto& e : s->ev) HIP_OK(hipEventCreate(&e));
   }
   if (timing) HIP_OK(hipEventRecord(s->ev[2 * max_iters], st));
