@@ -27,7 +27,9 @@
  *     caller; outputs go to caller buffers.  A mace_system owns its device
  *     memory until mace_free_system().  Calls on one mace_system must not
  *     overlap (the system holds the scan workspaces and runs every solve on
- *     one private stream).
+ *     one private stream); calls on different systems may run on different
+ *     host threads at the same time (the library serializes its graph
+ *     captures with its allocations internally).
  *   - Device-pointer variants (suffix _dev) take device addresses and a HIP
  *     stream (hipStream_t passed as void*, NULL = default stream); they
  *     wait for the work already queued on that stream, run on the system's
