@@ -14,6 +14,10 @@ paper's order:
   * partial-update MACE (Algorithm 1) with the Mann update (eq. (Mann));
   * the exact proximal map by repeated passes, and the centralised ICD baseline
     (Sec. IV-B).
+The Python side adds partial-update MACE with PnP priors (Algorithm 3, Sec.
+III): the agents' data terms alone (prior kind PRIOR_NONE, beta = 0) at
+sqrt(N) sigma, and the consensus G_H(v) = H(mean v) with a stand-in denoiser H
+(``binomial_smooth``, a linear smoother that is firmly non-expansive).
 Reading of the prior (the paper names the Q-GGMRF prior without its formula):
   rho(d) = |d|^p/(p sigma_x^p) / (1 + (|d|/(T sigma_x))^(p-q)); quadratic prior
   rho(d) = d^2/(2 sigma_x^2); 8-neighbour cliques, each unordered pair once;
@@ -34,6 +38,26 @@ _LIB = os.path.join(_LIB_DIR, "libmace_oracle.so")
 
 MODE_SURROGATE = 0
 MODE_EXACT = 1
+PRIOR_QUADRATIC = 0
+PRIOR_QGGMRF = 1
+PRIOR_NONE = 2  # beta = 0: the data term alone (MACE-PnP agents)
+
+
+def binomial_smooth(x, nx, ny, passes):
+    """Stand-in PnP denoiser H: `passes` applications of the 3x3 binomial
+    filter (1/4, 1/2, 1/4) along rows, then along columns, with zero values
+    outside the image.  Per axis the filter is the symmetric tridiagonal
+    matrix tridiag(1/4, 1/2, 1/4), whose eigenvalues 1/2 + 1/2 cos(k pi/(m+1))
+    lie in (0, 1); so H is symmetric with spectrum in (0, 1), i.e. firmly
+    non-expansive, and it is the proximal map of the quadratic
+    phi(x) = x^T (H^-1 - I) x / 2."""
+    img = np.asarray(x, dtype=np.float64).reshape(ny, nx)
+    for _ in range(int(passes)):
+        pad = np.zeros((ny + 2, nx + 2))
+        pad[1:-1, 1:-1] = img
+        rows = 0.25 * pad[:, :-2] + 0.5 * pad[:, 1:-1] + 0.25 * pad[:, 2:]
+        img = 0.25 * rows[:-2, :] + 0.5 * rows[1:-1, :] + 0.25 * rows[2:, :]
+    return img.reshape(-1)
 
 
 def build(force: bool = True) -> str:
@@ -195,6 +219,40 @@ class Oracle:
                                    float(relax), _p(x), _p(X), _p(res))
         return dict(x=x, w=w.reshape(self.N, self.n), X=X.reshape(self.N, self.n),
                     resid=res[:k], iters=int(k))
+
+    # ---- Algorithm 3 (partial-update MACE with PnP priors) ----
+    def mace_pnp_solve(self, rho, sigma, max_iters, h_passes, sweeps=1, order=None,
+                       relax=1.0):
+        """Algorithm 3 with F of eq. (FG_PnP): each agent's partial update is
+        `sweeps` ICD passes on its data term alone (the oracle must be built
+        with prior_kind PRIOR_NONE) at sqrt(N) sigma, starting from its
+        previous state; G_H(w) = H(mean_i w_i) for every agent, H =
+        binomial_smooth(., h_passes); w^0 = 0, X^0 = G_H(w^0).  Returns
+        dict(x = H(mean w), w, X, resid) with the residual of Algorithm 1's
+        statistic, ||X^{k+1} - G_H(w^k)|| / ||w^k||."""
+        N, n = self.N, self.n
+
+        def H(v):
+            return binomial_smooth(v, self.nx, self.ny, h_passes)
+
+        w = np.zeros((N, n))
+        X = np.tile(H(w.mean(axis=0)), (N, 1))
+        e = [self.error_sinogram(X[i], agent=i) for i in range(N)]
+        sp = float(sigma) * np.sqrt(N)
+        resid = []
+        for _ in range(int(max_iters)):
+            g = H(w.mean(axis=0))            # one copy of G_H(w^k)
+            v = 2.0 * g[None, :] - w         # v^k = (2 G_H - I) w^k
+            for i in range(N):
+                for _ in range(int(sweeps)):
+                    self.icd_pass(i, sp, v[i], X[i], e[i], order=order, relax=relax)
+            num = np.linalg.norm(X - g[None, :])
+            den = np.linalg.norm(w)
+            if den == 0.0:
+                den = np.linalg.norm(X)
+            resid.append(num / den if den > 0 else 0.0)
+            w = rho * (2.0 * X - v) + (1.0 - rho) * w
+        return dict(x=H(w.mean(axis=0)), w=w, X=X, resid=np.array(resid))
 
     def prox(self, agent, sigma, v, z0=None, max_passes=100000, rtol=1e-14,
              mode=MODE_EXACT):

@@ -65,7 +65,7 @@ typedef struct {
   const float* lam;
   int32_t n_agents;
   const int32_t* view_agent; /* [n_views] */
-  int32_t prior_kind;        /* 0 quadratic, 1 q-GGMRF */
+  int32_t prior_kind;        /* 0 quadratic, 1 q-GGMRF, 2 none (beta = 0, Sec. III) */
   double sigma_x, p, q, T, b_edge, b_diag;
 } orc_in;
 
@@ -86,6 +86,7 @@ typedef struct {
 /* ---------------- prior potential ---------------- */
 
 static double pot(const orc_state* S, double d) {
+  if (S->kind == 2) return 0.0;
   if (S->kind == 0) return d * d / (2.0 * S->sx * S->sx);
   double u = fabs(d);
   double s = pow(u / (S->T * S->sx), S->p - S->q);
@@ -93,6 +94,7 @@ static double pot(const orc_state* S, double d) {
 }
 
 static double pot_d1(const orc_state* S, double d) {
+  if (S->kind == 2) return 0.0;
   if (S->kind == 0) return d / (S->sx * S->sx);
   double u = fabs(d);
   if (u == 0.0) return 0.0;
@@ -104,6 +106,7 @@ static double pot_d1(const orc_state* S, double d) {
 
 /* c(d) = rho'(d)/d, the curvature of the symmetric quadratic majoriser. */
 static double pot_curv(const orc_state* S, double d) {
+  if (S->kind == 2) return 0.0;
   if (S->kind == 0) return 1.0 / (S->sx * S->sx);
   double u = fabs(d);
   double s = pow(u / (S->T * S->sx), S->p - S->q);
@@ -326,7 +329,7 @@ int orc_icd_pass(const orc_state* S, int agent, double sigma, const double* v,
     double zs = z[s];
     double dv = (sigma > 0 && v) ? zs - v[s] : 0.0;
     double alpha;
-    if (mode == 0 || S->kind == 0) {
+    if (mode == 0 || S->kind != 1) {
       double gp = 0.0, hp = 0.0;
       for (int k = 0; k < c; ++k) {
         double d = zs - z[nb[k]];

@@ -10,6 +10,11 @@ P4  the agent cost never increases during a pass (both coordinate rules)
 P5  partial-update MACE == the exact augmented linear map of Theorem 2; its
     limit is the map's fixed point
 P6  special cases: N = 1, q-GGMRF limits (p = q, T -> inf, large |d|)
+P7  MACE-PnP (Algorithm 3): the stand-in denoiser's spectrum equals the closed
+    form of the binomial filter (symmetric, in (0, 1): firmly non-expansive),
+    and the PnP fixed point is the minimiser of f(x) + phi(x)/sigma^2 with
+    H = prox of phi (dense solve), every agent's state equal to H(mean w)
+    (Theorem 3, Appendix C)
 plus the divergence of Algorithm 1 at sigma = 0.05 on the 64x64 workload.
 """
 import numpy as np
@@ -309,3 +314,41 @@ def test_P8_oracle_is_deterministic():
     a = O.mace_solve(0.8, 0.003, 20)
     b = O.mace_solve(0.8, 0.003, 20)
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["resid"], b["resid"])
+
+
+# ---------------- P7: MACE-PnP ----------------
+def _dense_smoother(nx, ny, passes):
+    n = nx * ny
+    return np.stack([oracle.binomial_smooth(np.eye(n)[j], nx, ny, passes) for j in range(n)],
+                    axis=1)
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_P7_denoiser_spectrum_is_the_binomial_closed_form(passes):
+    nx, ny = 5, 4
+    Hm = _dense_smoother(nx, ny, passes)
+    assert np.array_equal(Hm, Hm.T)
+    # per axis tridiag(1/4, 1/2, 1/4): eigenvalues 1/2 + 1/2 cos(k pi / (m + 1))
+    lx = 0.5 + 0.5 * np.cos(np.arange(1, nx + 1) * np.pi / (nx + 1))
+    ly = 0.5 + 0.5 * np.cos(np.arange(1, ny + 1) * np.pi / (ny + 1))
+    ref = np.sort(np.outer(ly, lx).reshape(-1) ** passes)
+    got = np.sort(np.linalg.eigvalsh(Hm))
+    assert np.allclose(got, ref, rtol=0, atol=1e-14)
+    assert got.min() > 0.0 and got.max() < 1.0
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_P7_pnp_fixed_point_is_the_pnp_map(passes):
+    """H = prox of phi(x) = x^T (H^-1 - I) x / 2, so the PnP equilibrium
+    F(x - a; sigma) = x, H(x + a) = x is the minimiser of
+    f(x) + phi(x) / sigma^2 (f without prior); MACE-PnP with F_i at
+    sqrt(N) sigma reaches it, with X_i = H(mean w) for every agent."""
+    g = mi.Geometry(10, 10, 24, 16)
+    N, sigma = 3, 0.001
+    O, A, lam, y, va = _problem(g, 41, N, kind=oracle.PRIOR_NONE, sx=1.0)
+    res = O.mace_pnp_solve(0.8, sigma, 3000, passes)
+    M = np.linalg.inv(_dense_smoother(g.nx, g.ny, passes)) - np.eye(g.n)
+    xref = np.linalg.solve(A.T @ (lam[:, None] * A) + M / sigma ** 2, A.T @ (lam * y))
+    assert res["resid"][-1] < 1e-12
+    assert np.linalg.norm(res["x"] - xref) <= 1e-10 * np.linalg.norm(xref)
+    assert np.abs(res["X"] - res["x"][None, :]).max() <= 1e-10 * np.abs(res["x"]).max()
