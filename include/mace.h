@@ -145,6 +145,26 @@ int mace_solve(mace_system* sys, const float* y, const float* lambda, const mace
                double rho, double sigma, int32_t sweeps, int32_t max_iters, double tol,
                const float* w_init, float* x_out, mace_info* info);
 
+/*
+ * Partial-update MACE with a plug-and-play prior (Algorithm 3, Sec. III):
+ * the agents apply partial updates of the proximal maps of their data terms
+ * alone (beta = 0, no prior), F_i(v; sqrt(N) sigma) (eq. (FG_PnP)), and the
+ * consensus operator is G_H(w) = H(mean_i w_i) for every agent, with the
+ * Mann iteration of eq. (Mann_PnP).  The denoiser H here is h_passes
+ * applications of the 3x3 binomial smoother (1/4, 1/2, 1/4 along rows, then
+ * along columns, zero outside the image): symmetric with its spectrum in
+ * (0, 1), hence firmly non-expansive (the case of the lemma of Sec. III that
+ * makes T_H non-expansive), and the proximal
+ * map of x^T (H^-1 - I) x / 2, so the fixed point is the minimiser of
+ * f(x) + x^T (H^-1 - I) x / (2 sigma^2) (Theorem 3).  w starts at 0; x_out
+ * [nx*ny] receives x* = H(mean_i w_i).  The residual and stopping test are
+ * those of mace_solve with G_H in place of G.  h_passes in [1, 64].
+ * Errors: as mace_solve.
+ */
+int mace_solve_pnp(mace_system* sys, const float* y, const float* lambda, double rho,
+                   double sigma, int32_t sweeps, int32_t max_iters, double tol, int32_t h_passes,
+                   float* x_out, mace_info* info);
+
 /* Device-pointer variant of mace_solve (all arrays in device memory). */
 int mace_solve_dev(mace_system* sys, const float* y, const float* lambda,
                    const mace_prior* prior, double rho, double sigma, int32_t sweeps,

@@ -79,6 +79,8 @@ def _load():
     L.mace_load_system.restype = ctypes.c_int
     L.mace_solve.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, P(Info)]
     L.mace_solve.restype = ctypes.c_int
+    L.mace_solve_pnp.argtypes = [vp, vp, vp, d, d, i32, i32, d, i32, vp, P(Info)]
+    L.mace_solve_pnp.restype = ctypes.c_int
     L.mace_solve_dev.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, P(Info), vp]
     L.mace_solve_dev.restype = ctypes.c_int
     L.mace_solve_batch.argtypes = [vp, i32, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp]
@@ -128,7 +130,7 @@ def _load():
 _lib = _load()
 
 # Entry points of the C ABI, by name.
-EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_dev", "mace_solve_batch",
+EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_pnp", "mace_solve_dev", "mace_solve_batch",
             "mace_solve_batch_dev", "mace_prox", "mace_visit_order", "mace_get_state",
             "mace_get_error_sinogram", "mace_system_bytes", "mace_scan_bytes",
             "mace_check_layout", "mace_set_timing", "mace_set_relaxation", "mace_server_create",
@@ -258,6 +260,21 @@ class System:
         rc = _lib.mace_solve(self._h, _ptr(yy), _ptr(ll), ctypes.byref(prior), float(rho),
                              float(sigma), int(sweeps), int(max_iters), float(tol), _ptr(wi),
                              _ptr(x), ctypes.byref(info))
+        _check(rc)
+        return x, info
+
+    def solve_pnp(self, y, lam, rho, sigma, max_iters, h_passes=1, tol=0.0, sweeps=1):
+        """MACE with the stand-in PnP denoiser (C ABI mace_solve_pnp): host
+        arrays in, (x = H(mean w), info) out."""
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        ll = np.ascontiguousarray(lam, dtype=np.float32)
+        if yy.size != self.n_rows or ll.size != self.n_rows:
+            raise ValueError("y / lambda have the wrong size")
+        x = np.empty(self.n, dtype=np.float32)
+        info = Info()
+        rc = _lib.mace_solve_pnp(self._h, _ptr(yy), _ptr(ll), float(rho), float(sigma),
+                                 int(sweeps), int(max_iters), float(tol), int(h_passes), _ptr(x),
+                                 ctypes.byref(info))
         _check(rc)
         return x, info
 

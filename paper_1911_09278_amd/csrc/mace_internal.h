@@ -34,7 +34,9 @@ struct SlotDesc {
   const float* lam;   // inverse-variance weights, agent blocks
   float* X;           // [N][n] agent states
   float* w;           // [N][n] Mann state
-  float* wbar;        // [n] mean of w (updated by the epilogue)
+  float* wbar;        // [n] mean of w (updated by the epilogue); with a PnP
+                      // denoiser H, H(mean of w)
+  float* aux;         // [n] scratch of the denoiser passes
   float* th2;         // [N][n] theta2 = sum_r A_rs^2 Lambda_r
   double* part;       // [N * n_sv][4] FP64 residual partials per task, then
                       // the epilogue's per-block sums
@@ -75,6 +77,7 @@ struct SvArgs {
   int strict;           // one SV of an agent at a time: stage e after the previous flush
   int rpb;              // rows per workgroup (16, 8 or 4); the block has rpb * 16 threads
   int kstr;             // record values per (agent, pixel): the largest view count of an agent
+  int hpass;            // MACE-PnP: passes of the denoiser H after each epilogue (0: plain MACE)
 };
 
 // Per-variant sweep launchers (mace_sweep_*.hip).
@@ -93,6 +96,10 @@ size_t sv_lds_bytes(int bmax, int S, int kpad);
 size_t epilogue_scratch_doubles();
 hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int nparts,
                            hipStream_t st);
+// MACE-PnP consensus G_H: `passes` applications of the 3x3 binomial smoother
+// to every active slot's wbar (through its aux buffer).
+hipError_t launch_smooth(const SlotDesc* slots, int n_slots, int nx, int ny, int passes,
+                         hipStream_t st);
 hipError_t launch_gather_rows(float* dst, const float* src, const int* row_src, int64_t count,
                               hipStream_t st);
 hipError_t launch_fill(float* dst, float v, int64_t count, hipStream_t st);

@@ -141,6 +141,41 @@ hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int
 
 size_t epilogue_scratch_doubles() { return (size_t)kEpiRedBlocks * 4; }
 
+// ---------------- MACE-PnP consensus: G_H(w) = H(mean w) ----------------
+
+// One axis of the binomial smoother (1/4, 1/2, 1/4) with zero values outside
+// the image: along rows wbar -> aux (COLS = false), along columns aux -> wbar.
+template <bool COLS>
+__global__ __launch_bounds__(256) void smooth_kernel(const SlotDesc* __restrict__ slots, int nx,
+                                                     int ny) {
+  const SlotDesc d = slots[blockIdx.y];
+  if (!d.active) return;
+  const float* src = COLS ? d.aux : d.wbar;
+  float* dst = COLS ? d.wbar : d.aux;
+  const int n = nx * ny;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+    const int i = s / nx, j = s - (s / nx) * nx;
+    const int step = COLS ? nx : 1;
+    const bool lo = COLS ? i > 0 : j > 0;
+    const bool hi = COLS ? i < ny - 1 : j < nx - 1;
+    const float a = lo ? src[s - step] : 0.0f;
+    const float c = hi ? src[s + step] : 0.0f;
+    dst[s] = 0.25f * a + 0.5f * src[s] + 0.25f * c;
+  }
+}
+
+hipError_t launch_smooth(const SlotDesc* slots, int n_slots, int nx, int ny, int passes,
+                         hipStream_t st) {
+  if (n_slots <= 0 || passes <= 0) return hipSuccess;
+  int gx = (nx * ny + 255) / 256;
+  if (gx > kEpiBlocks) gx = kEpiBlocks;
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL(smooth_kernel<false>, dim3(gx, n_slots), dim3(256), 0, st, slots, nx, ny);
+    hipLaunchKernelGGL(smooth_kernel<true>, dim3(gx, n_slots), dim3(256), 0, st, slots, nx, ny);
+  }
+  return hipGetLastError();
+}
+
 // ---------------- small helpers ----------------
 
 __global__ void gather_rows_kernel(float* __restrict__ dst, const float* __restrict__ src,

@@ -71,13 +71,13 @@ struct Schedule {
 
 // Device state of one scan.
 struct ScanSlot {
-  DevBuf<float> e, lam, yb, X, w, wbar, th2;
+  DevBuf<float> e, lam, yb, X, w, wbar, aux, th2;
   DevBuf<double> part, resid;
   DevBuf<int> counter;
   int resid_cap = 0;
   int64_t bytes() const {
     return (int64_t)(e.bytes() + lam.bytes() + yb.bytes() + X.bytes() + w.bytes() + wbar.bytes() +
-                     th2.bytes() + part.bytes() + resid.bytes() + counter.bytes());
+                     aux.bytes() + th2.bytes() + part.bytes() + resid.bytes() + counter.bytes());
   }
 };
 

@@ -20,7 +20,7 @@ namespace mace {
 
 int64_t slot_bytes(const mace_system* s, int resid_cap) {
   const int64_t nimg = (int64_t)s->N * s->n, nrow = (int64_t)s->N * s->estride;
-  return 4 * (3 * nrow + 3 * nimg + s->n) +
+  return 4 * (3 * nrow + 3 * nimg + 2 * s->n) +
          8 * ((int64_t)s->N * s->n_sv * 4 + (int64_t)epilogue_scratch_doubles() + std::max(1, resid_cap)) + 8;
 }
 
@@ -38,6 +38,7 @@ int ensure_slot(mace_system* s, Batch& b, int idx, int resid_cap) {
     HIP_OK(q.w.alloc(nimg));
     HIP_OK(q.th2.alloc(nimg));
     HIP_OK(q.wbar.alloc(s->n));
+    HIP_OK(q.aux.alloc(s->n));
     HIP_OK(q.part.alloc((size_t)s->N * s->n_sv * 4 + epilogue_scratch_doubles()));
     HIP_OK(q.counter.alloc(2));
     HIP_OK(hipMemset(q.counter.p, 0, 2 * sizeof(int)));  // the epilogue ticket starts at 0
@@ -71,6 +72,7 @@ int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st) {
     d.X = q.X.p;
     d.w = q.w.p;
     d.wbar = q.wbar.p;
+    d.aux = q.aux.p;
     d.th2 = q.th2.p;
     d.part = q.part.p;
     d.resid = q.resid.p;
@@ -121,6 +123,7 @@ int enqueue_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots
   }
   if (ev1) HIP_OK(hipEventRecord(ev1, st));
   HIP_OK(launch_epilogue(b.table.p, n_slots, s->N, s->n, s->N * s->n_sv, st));
+  if (a.hpass > 0) HIP_OK(launch_smooth(b.table.p, n_slots, s->nx, s->ny, a.hpass, st));
   return MACE_OK;
 }
 
@@ -135,6 +138,7 @@ uint64_t args_key(const SvArgs& a) {
   mix(&a.bedge, sizeof(float) * 6);
   mix(&a.fp16, sizeof a.fp16);
   mix(&a.strict, sizeof a.strict);
+  mix(&a.hpass, sizeof a.hpass);
   return h;
 }
 
@@ -258,7 +262,13 @@ struct BatchIO {
 // Each scan stops on its own residual; finished scans are switched off in the
 // slot table while the others continue.
 int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior* pr, double rho,
-                     double sigma, int sweeps, int max_iters, double tol, hipStream_t user) {
+                     double sigma, int sweeps, int max_iters, double tol, hipStream_t user,
+                     int hpass = 0) {
+  // MACE-PnP (Algorithm 3, eq. (FG_PnP)): the agents' proximal maps of the
+  // data terms alone (beta = 0) at sqrt(N) sigma; the consensus is
+  // H(mean w), `hpass` passes of the binomial smoother after each epilogue
+  const mace_prior none{0, 1.0, 2.0, 2.0, 1.0, 0.0, 0.0};
+  if (hpass > 0) pr = &none;
   int rc = check_prior(pr);
   if (rc) return rc;
   if (n < 1 || n > kMaxScanSlots) return fail(MACE_E_ARG, "batch size must be in [1, %d]", kMaxScanSlots);
@@ -280,8 +290,12 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
   }
   const bool fp16 = s->precision == 1;
   SvArgs a;
-  fill_args(s, a, pr, rho, sigma, fp16);
+  fill_args(s, a, pr, rho, hpass > 0 ? sigma * std::sqrt((double)s->N) : sigma, fp16);
   a.strict = P == 1 ? 1 : 0;
+  if (hpass > 0) {
+    a.c0 = 0.0f;  // no prior term in the agents
+    a.hpass = hpass;
+  }
   for (int i = 0; i < n; ++i) {
     rc = start_slot(s, b, i, io[i].y, io[i].lam, io[i].w_init, a, st);
     if (rc) return rc;
@@ -441,6 +455,25 @@ extern "C" int mace_solve(mace_system* s, const float* y, const float* lam, cons
   HIP_OK(dx.alloc(s->n));
   BatchIO io{dy.p, dl.p, w_init ? dw.p : nullptr, dx.p, info};
   int rc = solve_batch_impl(s, 1, &io, pr, rho, sigma, sweeps, max_iters, tol, nullptr);
+  if (rc < 0 && rc != MACE_E_NONFINITE) return rc;
+  const std::string saved = last_error_text();
+  HIP_OK(hipMemcpy(x_out, dx.p, sizeof(float) * s->n, hipMemcpyDeviceToHost));
+  if (rc == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "%s", saved.c_str());
+  return rc;
+}
+
+extern "C" int mace_solve_pnp(mace_system* s, const float* y, const float* lam, double rho,
+                              double sigma, int32_t sweeps, int32_t max_iters, double tol,
+                              int32_t h_passes, float* x_out, mace_info* info) {
+  if (!s || !y || !lam || !x_out) return fail(MACE_E_ARG, "NULL argument");
+  if (h_passes < 1 || h_passes > 64) return fail(MACE_E_ARG, "h_passes must be in [1, 64]");
+  const size_t m = (size_t)s->n_views * s->n_ch;
+  DevBuf<float> dy, dl, dx;
+  HIP_OK(dy.upload(y, m));
+  HIP_OK(dl.upload(lam, m));
+  HIP_OK(dx.alloc(s->n));
+  BatchIO io{dy.p, dl.p, nullptr, dx.p, info};
+  int rc = solve_batch_impl(s, 1, &io, nullptr, rho, sigma, sweeps, max_iters, tol, nullptr, h_passes);
   if (rc < 0 && rc != MACE_E_NONFINITE) return rc;
   const std::string saved = last_error_text();
   HIP_OK(hipMemcpy(x_out, dx.p, sizeof(float) * s->n, hipMemcpyDeviceToHost));

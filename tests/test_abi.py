@@ -163,6 +163,7 @@ def test_batch_and_autotune_reject_bad_arguments_without_a_device():
                               None, info) == m.MACE_E_ARG
     assert L.mace_solve_batch_dev(None, 2, None, None, ctypes.byref(pr), 0.8, 0.01, 1, 10, 0.0,
                                   None, info, None) == m.MACE_E_ARG
+    assert L.mace_solve_pnp(None, None, None, 0.8, 0.01, 1, 10, 0.0, 1, None, None) == m.MACE_E_ARG
     best = m.Opts()
     g = m.Geom(8, 8, 4, 8)
     assert L.mace_autotune(None, None, None, None, 2, None, None, 4, ctypes.byref(best), None,

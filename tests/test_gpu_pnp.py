@@ -1,0 +1,79 @@
+"""GPU parity of MACE with plug-and-play priors (Algorithm 3).
+
+The agents run partial updates of their data terms alone at sqrt(N) sigma
+and the consensus is G_H(w) = H(mean w) with the stand-in denoiser H (passes
+of the 3x3 binomial smoother).
+1. Sequential schedule: the GPU iterates (X, w) and x = H(mean w) follow the
+   oracle's Algorithm 3 in the same visiting order, element by element.
+2. Concurrent schedule: the fixed point is the minimiser of
+   f(x) + x^T (H^-1 - I) x / (2 sigma^2) (Theorem 3; dense solve).
+"""
+import numpy as np
+import pytest
+
+import mace_inputs as mi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1911_09278_amd as lib
+    return lib
+
+
+def _problem(g, seed, N):
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, seed)
+    va = mi.interleaved_partition(g.n_views, N)
+    O = oracle.Oracle(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, s.y, s.lam, va,
+                      oracle.PRIOR_NONE, 1.0)
+    return (cp, row, val), s, O
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_sequential_pnp_matches_oracle(m, passes):
+    g = mi.Geometry(32, 32, 64, 48)
+    N, sigma, iters = 4, 0.001, 5
+    (cp, row, val), s, O = _problem(g, 91, N)
+    print(f"sequential MACE-PnP 32x32 N={N} passes={passes}", flush=True)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=4,
+                    rows_per_agent=1)
+    x, info = sysm.solve_pnp(s.y, s.lam, 0.8, sigma, iters, h_passes=passes)
+    w, X = sysm.state()
+    ref = O.mace_pnp_solve(0.8, sigma, iters, passes, order=sysm.visit_order())
+    scale = np.abs(ref["X"]).max()
+    assert info.iters == iters and np.all(np.isfinite(x))
+    assert np.abs(X - ref["X"]).max() <= 5e-5 * scale, np.abs(X - ref["X"]).max() / scale
+    assert np.abs(w - ref["w"]).max() <= 5e-5 * np.abs(ref["w"]).max()
+    assert np.abs(x - ref["x"]).max() <= 5e-5 * np.abs(ref["x"]).max()
+    assert abs(info.residual - ref["resid"][-1]) <= 1e-3 * ref["resid"][-1] + 1e-7
+
+
+def test_concurrent_pnp_fixed_point_is_the_pnp_map(m):
+    """The agents have no prior term here, so only the prox term damps the
+    coupling of concurrently updated super-voxels: at sigma = 1e-3 this
+    schedule diverges; 1 / (N sigma^2) = 1e6 against theta2 ~ 1.6e5 keeps it
+    stable."""
+    from tests import dense_ref as dr
+    g = mi.Geometry(32, 32, 64, 48)
+    N, sigma, passes = 4, 5e-4, 1
+    (cp, row, val), s, O = _problem(g, 92, N)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N)
+    assert sysm.config["rows_per_agent"] > 1
+    sysm.set_relaxation(0.5)
+    x, info = sysm.solve_pnp(s.y, s.lam, 0.8, sigma, 4000, h_passes=passes, tol=1e-6)
+    print("iters", info.iters, "resid", info.residual, flush=True)
+    assert info.status == m.MACE_OK
+    A = dr.dense_A(g, cp, row, val)
+    Hm = np.stack([oracle.binomial_smooth(np.eye(g.n)[j], g.nx, g.ny, passes)
+                   for j in range(g.n)], axis=1)
+    M = np.linalg.inv(Hm) - np.eye(g.n)
+    lam, y = s.lam.astype(np.float64), s.y.astype(np.float64)
+    xref = np.linalg.solve(A.T @ (lam[:, None] * A) + M / sigma ** 2, A.T @ (lam * y))
+    err = float(np.linalg.norm(x - xref) / np.linalg.norm(xref))
+    print("nrmse vs dense PnP MAP", err, flush=True)
+    assert err <= 1e-4
