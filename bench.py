@@ -291,6 +291,37 @@ def bench_fp16(args, m, mi, torch):
     return out
 
 
+def bench_pnp(args, m, mi, torch):
+    """MACE-PnP (Algorithm 3) on the scan512 workload: the agents' data terms
+    alone at sqrt(N) sigma and the consensus H(mean w), H = one pass of the
+    3x3 binomial smoother.  Host arrays in and out (mace_solve_pnp): the time
+    includes 4.2 MB of y / Lambda uploads per scan.  A step = one scan, 60
+    Mann iterations."""
+    w = mi.WORKLOADS["scan512"]
+    g = w.geom
+    sigma, passes = 5e-5, 1
+    log("pnp: matrix")
+    cp, row, val = mi.system_matrix(g)
+    sc = mi.scan(g, w.seed)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents)
+    sysm.set_relaxation(0.5)
+    for _ in range(args.warmup):
+        sysm.solve_pnp(sc.y, sc.lam, w.rho, sigma, args.iters, h_passes=passes)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, info = sysm.solve_pnp(sc.y, sc.lam, w.rho, sigma, args.iters, h_passes=passes)
+    dt = (time.perf_counter() - t0) / args.steps
+    upd = args.iters * w.n_agents * g.n
+    out = _common("agent-voxel updates/s, MACE-PnP (binomial stand-in denoiser), 512x512",
+                  upd / dt, "voxel-updates/s", args.steps, args.warmup, dt * 1e3, "f32",
+                  {"workload": "scan512: 512x512 image, 720 views, 736 channels, 16 agents, "
+                               "no prior in the agents, H = 1 pass of the 3x3 binomial smoother, "
+                               "rho=0.8",
+                   "mann_iters": args.iters, "sigma": sigma, "h_passes": passes})
+    out.update({"final_residual": info.residual, "x_finite": bool(np.all(np.isfinite(x)))})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,11 +335,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--mode", default="scan", choices=("scan", "slices", "serve", "fp16"),
+    ap.add_argument("--mode", default="scan", choices=("scan", "slices", "serve", "fp16", "pnp"),
                     help="scan: the headline one-scan benchmark (default); slices: 64 "
                          "512x512 slices sharing one matrix, batched vs one at a time; "
                          "serve: Poisson arrivals of mixed-size scans through the server; "
-                         "fp16: 1024x1024 FP16 matrix values vs FP32")
+                         "fp16: 1024x1024 FP16 matrix values vs FP32; "
+                         "pnp: MACE-PnP with the binomial stand-in denoiser")
     ap.add_argument("--scans", type=int, default=30, help="serve: number of arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
     ap.add_argument("--slices", type=int, default=64, help="slices: batch size")
@@ -339,7 +371,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.mode != "scan":
-        out = {"slices": bench_slices, "serve": bench_serve, "fp16": bench_fp16}[args.mode](args, m, mi, torch)
+        out = {"slices": bench_slices, "serve": bench_serve, "fp16": bench_fp16,
+               "pnp": bench_pnp}[args.mode](args, m, mi, torch)
         print(json.dumps(out), flush=True)
         return
     w8 = mi.WORKLOADS["scan512"]
