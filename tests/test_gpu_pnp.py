@@ -77,3 +77,29 @@ def test_concurrent_pnp_fixed_point_is_the_pnp_map(m):
     err = float(np.linalg.norm(x - xref) / np.linalg.norm(xref))
     print("nrmse vs dense PnP MAP", err, flush=True)
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("passes", [1, 3])
+def test_full_size_pnp_consensus(m, passes):
+    """512x512, 720 views, 16 agents in the launch configuration the
+    benchmark times: the returned image is H(mean w) of the read-back agents'
+    states, element by element against the oracle's smoother in FP64, and the
+    residual falls from 5 to 20 iterations."""
+    w8 = mi.WORKLOADS["scan512"]
+    g = w8.geom
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, w8.seed)
+    print(f"full-size MACE-PnP 512x512 N={w8.n_agents} passes={passes}", flush=True)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w8.n_agents)
+    sysm.set_relaxation(0.5)
+    _, early = sysm.solve_pnp(s.y, s.lam, w8.rho, 5e-5, 5, h_passes=passes)
+    x, info = sysm.solve_pnp(s.y, s.lam, w8.rho, 5e-5, 20, h_passes=passes)
+    w, _ = sysm.state()
+    assert np.all(np.isfinite(x)) and np.isfinite(info.residual)
+    ref = oracle.binomial_smooth(w.astype(np.float64).mean(axis=0), g.nx, g.ny, passes)
+    scale = np.abs(ref).max()
+    assert scale > 0
+    err = np.abs(x - ref).max() / scale
+    print("max rel err", err, "residuals", early.residual, info.residual, flush=True)
+    assert err <= 1e-5, err
+    assert info.residual < early.residual
