@@ -109,6 +109,8 @@ LAYOUT_CASES = [
     # 75 to 128 views per agent: bands too large for 16 rows per workgroup
     (mi.Geometry(24, 24, 150, 40), 2, 8), (mi.Geometry(26, 26, 200, 40), 2, 4),
     (mi.Geometry(20, 20, 128, 32), 1, 8),
+    # 4 views on 8 channels: empty columns, one view per agent
+    (mi.Geometry(24, 24, 4, 8), 4, 4), (mi.Geometry(24, 24, 4, 8), 2, 8),
 ]
 
 

@@ -57,6 +57,10 @@ SEQ_CASES = [
     (mi.Geometry(24, 24, 150, 40), 2, 1, 0.002, 1.2, 0.002, 8, 3, 1.0),  # 75 views: 5 slots, 8 rows
     (mi.Geometry(26, 26, 200, 40), 2, 0, 0.002, 2.0, 0.002, 4, 3, 1.0),  # 100 views: 7 slots, 16 rows
     (mi.Geometry(20, 20, 128, 32), 1, 1, 0.003, 1.5, 0.003, 8, 3, 1.0),  # 128 views: 8 slots (most)
+    # 4 views on 8 channels: 24 pixels no ray crosses (empty columns of A),
+    # and with one view per agent most of each agent's columns are empty
+    (mi.Geometry(24, 24, 4, 8), 4, 1, 0.003, 1.2, 0.003, 4, 4, 1.0),
+    (mi.Geometry(24, 24, 4, 8), 2, 0, 0.003, 2.0, 0.003, 8, 4, 1.0),
 ]
 
 

@@ -275,6 +275,21 @@ def test_P6_single_agent_reaches_centralised_map():
     assert np.linalg.norm(xc - xmap) / np.linalg.norm(xmap) < 1e-9
 
 
+def test_P2_empty_columns_fixed_point_is_the_map():
+    """4 views on 8 channels leave 24 pixels that no ray crosses (empty
+    columns of A), and with one view per agent most of each agent's columns
+    are empty: there the update is set by the prior and the prox term alone,
+    and the fixed point is still the dense MAP (Theorem 1)."""
+    g = mi.Geometry(24, 24, 4, 8)
+    sx = 0.003
+    O, A, lam, y, va = _problem(g, 125, 4, 0, sx)
+    assert int((np.abs(A).sum(axis=0) == 0).sum()) == 24
+    xmap = dr.map_quadratic(A, lam, y, dr.laplacian(g.nx, g.ny), sx)
+    r = O.mace_solve(0.8, 0.003, 20000, tol=1e-13)
+    assert r["resid"][-1] < 1e-13
+    assert np.linalg.norm(r["x"] - xmap) / np.linalg.norm(xmap) < 1e-9
+
+
 def test_P6_reflection_is_an_involution():
     rng = np.random.default_rng(6)
     N, n = 5, 7
