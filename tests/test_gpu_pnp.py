@@ -103,3 +103,28 @@ def test_full_size_pnp_consensus(m, passes):
     print("max rel err", err, "residuals", early.residual, info.residual, flush=True)
     assert err <= 1e-5, err
     assert info.residual < early.residual
+
+
+def test_full_size_pnp_residual_and_concurrency(m):
+    """512x512, 16 agents.  With no prior term in the agents, 512 concurrent
+    super-voxels per agent (the automatic value) leave the residual near
+    4e-4 while the image converges; 32 per agent converge like the sequential
+    schedule (r < 1e-6 after 600 iterations), and the two images agree."""
+    w8 = mi.WORKLOADS["scan512"]
+    g = w8.geom
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, w8.seed)
+    print("full-size MACE-PnP 512x512 N=16, 32 and 512 rows per agent", flush=True)
+    low = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w8.n_agents,
+                   rows_per_agent=32)
+    low.set_relaxation(0.5)
+    x32, i32 = low.solve_pnp(s.y, s.lam, w8.rho, 5e-5, 600, h_passes=1)
+    low.close()
+    dflt = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w8.n_agents)
+    dflt.set_relaxation(0.5)
+    xd, idf = dflt.solve_pnp(s.y, s.lam, w8.rho, 5e-5, 600, h_passes=1)
+    d = float(np.linalg.norm(xd.astype(np.float64) - x32) / np.linalg.norm(x32))
+    print("residuals", i32.residual, idf.residual, "image NRMSE", d, flush=True)
+    assert i32.residual < 1e-6
+    assert np.isfinite(idf.residual) and idf.residual < 2e-3
+    assert d < 1e-3, d
