@@ -391,11 +391,16 @@ def bench_study(args, m, mi, torch):
         ks, es = [], []
         ref = float(np.linalg.norm(x_star))
         for k in study_grid(k_max):
-            if pnp:
-                x, _ = s.solve_pnp(sc.y, sc.lam, rho, sigma, k, h_passes=1)
-            else:
-                x, _ = s.solve(sc.y, sc.lam, prior, rho, sigma, k)
-            e = float(np.linalg.norm(x.astype(np.float64) - x_star)) / ref
+            try:
+                if pnp:
+                    x, _ = s.solve_pnp(sc.y, sc.lam, rho, sigma, k, h_passes=1)
+                else:
+                    x, _ = s.solve(sc.y, sc.lam, prior, rho, sigma, k)
+                e = float(np.linalg.norm(x.astype(np.float64) - x_star)) / ref
+            except m.MaceError as err:  # a diverging iteration
+                if err.code != m.MACE_E_NONFINITE:
+                    raise
+                e = float("inf")
             ks.append(k)
             es.append(e if np.isfinite(e) else float("inf"))
             if not np.isfinite(e) or e > 10.0:

@@ -32,7 +32,7 @@ hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds,
 
 // For every active slot (blockIdx.y): wbar[s] = mean_i w[i][s], and the
 // slot's residual r_k = sqrt(num) / sqrt(den > 0 ? den : ||X||^2) from the
-// per-task FP64 partials.  The partials are summed in a fixed order whatever
+// per-task FP64 partials (NaN when a partial sum is not finite).  The partials are summed in a fixed order whatever
 // the timing: each of the first kEpiRedBlocks blocks sums a fixed chunk and
 // stores its sums after the task partials; the one of those that arrives
 // last (ticket in counter[1]) adds the block sums in block order, stores r_k
@@ -122,7 +122,10 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
   if (tid == 0) {
     const int k = d.counter[0];
     const double den = bs[1] > 0.0 ? bs[1] : bs[2];
-    const double r = den > 0.0 ? sqrt(bs[0]) / sqrt(den) : 0.0;
+    // a non-finite state (a diverging iteration) makes r non-finite too, so
+    // the stopping test can never take it for convergence
+    const bool finite = isfinite(bs[0]) && isfinite(bs[1]) && isfinite(bs[2]);
+    const double r = !finite ? __builtin_nan("") : den > 0.0 ? sqrt(bs[0]) / sqrt(den) : 0.0;
     if (k < d.resid_cap) d.resid[k] = r;
     *d.last = r;
     d.counter[0] = k + 1;

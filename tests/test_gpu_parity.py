@@ -310,3 +310,24 @@ def test_full_size_scan1024_fp16(m):
     err = _nrmse(xs[1], xs[0].astype(np.float64))
     print("fp16 vs fp32 nrmse", err, flush=True)
     assert err <= 1e-3
+
+
+def test_diverging_iteration_is_reported_not_converged(m):
+    """At 512x512 with 16 agents the iteration diverges for sigma = 3e-3 (the
+    stable sigma there is about 2e-4) and its states become NaN.  The solve
+    ends with MACE_E_NONFINITE with or without a stopping tolerance, never as
+    converged, and the system stays usable."""
+    w8 = mi.WORKLOADS["scan512"]
+    g = w8.geom
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, w8.seed)
+    print("diverging sigma 3e-3 at 512x512 N=16", flush=True)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w8.n_agents)
+    sysm.set_relaxation(0.5)
+    prior = m.make_prior(w8.prior_kind, w8.sigma_x, w8.p, w8.q, w8.T)
+    for tol in (0.0, 1e-4):
+        with pytest.raises(m.MaceError) as e:
+            sysm.solve(s.y, s.lam, prior, w8.rho, 3e-3, 120, tol=tol)
+        assert e.value.code == m.MACE_E_NONFINITE, (tol, e.value)
+    x, info = sysm.solve(s.y, s.lam, prior, w8.rho, 1e-4, 5)
+    assert np.all(np.isfinite(x)) and np.isfinite(info.residual) and info.residual > 0
