@@ -129,7 +129,7 @@ extern "C" int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, cons
       mace_info info{};
       // warm-up (also captures the iteration graph), then the timed solve
       rc = mace_solve(sys, y.data(), lam.data(), &pr, 0.8, sigma, 1, 2, 0.0, nullptr, x.data(), &info);
-      if (rc < 0) {
+      if (rc < 0 && rc != MACE_E_NONFINITE) {  // a diverging candidate is only marked
         mace_free_system(sys);
         return rc;
       }
