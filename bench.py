@@ -373,6 +373,8 @@ def bench_study(args, m, mi, torch):
     prior = m.make_prior(w.prior_kind, w.sigma_x, w.p, w.q, w.T)
     thresholds = (0.3, 0.2)
     pnp_thresholds = (1e-2, 1e-3)
+    # the longest curve: --iters when given, else 400 (the scan default of 60
+    # is far too short for these curves)
     k_max = args.iters if args.iters != 60 else 400
     agent_counts = (6, 8, 12, 16, 24, 48)
     log("study: matrix")
