@@ -34,7 +34,7 @@ def _problem(g, seed, N):
     return (cp, row, val), s, O
 
 
-@pytest.mark.parametrize("passes", [1, 2])
+@pytest.mark.parametrize("passes", [1, 2, 64])  # 64: the most the library accepts
 def test_sequential_pnp_matches_oracle(m, passes):
     g = mi.Geometry(32, 32, 64, 48)
     N, sigma, iters = 4, 0.001, 5
@@ -128,3 +128,15 @@ def test_full_size_pnp_residual_and_concurrency(m):
     assert i32.residual < 1e-6
     assert np.isfinite(idf.residual) and idf.residual < 2e-3
     assert d < 1e-3, d
+
+
+def test_pnp_rejects_denoiser_passes_out_of_range(m):
+    g = mi.Geometry(16, 16, 16, 24)
+    (cp, row, val), s, _ = _problem(g, 3, 2)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2)
+    for passes in (0, 65):
+        with pytest.raises(m.MaceError) as e:
+            sysm.solve_pnp(s.y, s.lam, 0.8, 1e-3, 2, h_passes=passes)
+        assert e.value.code == m.MACE_E_ARG and "h_passes" in str(e.value)
+    x, _ = sysm.solve_pnp(s.y, s.lam, 0.8, 1e-3, 2, h_passes=64)
+    assert np.all(np.isfinite(x))
