@@ -44,25 +44,30 @@ __device__ __forceinline__ double load_l2(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Sum over a 64-lane wave (butterfly, the same order on every call).
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sums of three values over a block of 256 threads (four waves): each wave
+// reduces its lanes, then thread 0 adds the four wave sums in wave order.
 __device__ void block_sum3(double s0, double s1, double s2, double* out) {
-  __shared__ double red[3][256];
-  const int tid = threadIdx.x;
-  red[0][tid] = s0;
-  red[1][tid] = s1;
-  red[2][tid] = s2;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) {
-      red[0][tid] += red[0][tid + h];
-      red[1][tid] += red[1][tid + h];
-      red[2][tid] += red[2][tid + h];
-    }
-    __syncthreads();
+  __shared__ double red[3][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  s0 = wave_sum64(s0);
+  s1 = wave_sum64(s1);
+  s2 = wave_sum64(s2);
+  if (lane == 0) {
+    red[0][wave] = s0;
+    red[1][wave] = s1;
+    red[2][wave] = s2;
   }
+  __syncthreads();
   if (tid == 0) {
-    out[0] = red[0][0];
-    out[1] = red[1][0];
-    out[2] = red[2][0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
   }
   __syncthreads();
 }
