@@ -111,6 +111,7 @@ LAYOUT_CASES = [
     (mi.Geometry(20, 20, 128, 32), 1, 8),
     # 4 views on 8 channels: empty columns, one view per agent
     (mi.Geometry(24, 24, 4, 8), 4, 4), (mi.Geometry(24, 24, 4, 8), 2, 8),
+    (mi.Geometry(21, 19, 40, 32), 2, 4),
 ]
 
 

@@ -61,6 +61,8 @@ SEQ_CASES = [
     # and with one view per agent most of each agent's columns are empty
     (mi.Geometry(24, 24, 4, 8), 4, 1, 0.003, 1.2, 0.003, 4, 4, 1.0),
     (mi.Geometry(24, 24, 4, 8), 2, 0, 0.003, 2.0, 0.003, 8, 4, 1.0),
+    # an odd pixel count (399)
+    (mi.Geometry(21, 19, 40, 32), 2, 1, 0.003, 1.2, 0.003, 4, 4, 1.0),
 ]
 
 
