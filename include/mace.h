@@ -139,7 +139,9 @@ int mace_load_system(const mace_geom* geom, const int64_t* col_ptr, const int32_
  * 0; the fixed point does not depend on it).  Stops after max_iters Mann
  * iterations or when r_k < tol (tol <= 0: never); x_out[nx*ny] receives the
  * consensus image mean_i w_i.  info (optional) receives the statistics.
- * Returns MACE_OK, MACE_W_MAXITER (tol > 0 not reached), or an error.
+ * Returns MACE_OK, MACE_W_MAXITER (tol > 0 not reached), MACE_E_NONFINITE
+ * (the iteration diverged: its state or residual is not finite, with or
+ * without tol; x_out then holds non-finite values), or another error.
  */
 int mace_solve(mace_system* sys, const float* y, const float* lambda, const mace_prior* prior,
                double rho, double sigma, int32_t sweeps, int32_t max_iters, double tol,
