@@ -13,7 +13,10 @@ paper's order:
     surrogate step (mode 0) or the exact 1-D minimiser (mode 1);
   * partial-update MACE (Algorithm 1) with the Mann update (eq. (Mann));
   * the exact proximal map by repeated passes, and the centralised ICD baseline
-    (Sec. IV-B).
+    (Sec. IV-B);
+  * the MAP image of the quadratic prior by preconditioned conjugate gradients
+    on the normal equations of eq. (global_obj) (an algorithm independent of
+    ICD and MACE, for fixed-point checks at sizes a dense solve cannot reach).
 The Python side adds partial-update MACE with PnP priors (Algorithm 3, Sec.
 III): the agents' data terms alone (prior kind PRIOR_NONE, beta = 0) at
 sqrt(N) sigma, and the consensus G_H(v) = H(mean v) with a stand-in denoiser H
@@ -114,6 +117,8 @@ def _load():
         L.orc_prox.restype = i32
         L.orc_centralized_icd.argtypes = [vp, vp, i32, d, i32]
         L.orc_centralized_icd.restype = i32
+        L.orc_map_cg.argtypes = [vp, vp, i32, d, vp]
+        L.orc_map_cg.restype = i32
         L.orc_num_threads.restype = i32
         _lib = L
     return _lib
@@ -262,6 +267,18 @@ class Oracle:
         it = _load().orc_prox(self._h, int(agent), float(sigma), _p(vd), _p(z),
                               int(max_passes), float(rtol), int(mode))
         return z, int(it)
+
+    def map_cg(self, x0=None, max_iters=100000, rtol=1e-13):
+        """MAP image for the quadratic prior: the normal equations
+        (A^T Lambda A + L_b / sigma_x^2) x = A^T Lambda y of eq. (global_obj)
+        solved by Jacobi-preconditioned conjugate gradients.  Returns
+        (x, iterations, ||b - H x|| / ||b||)."""
+        x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64)
+        rr = np.zeros(1)
+        it = _load().orc_map_cg(self._h, _p(x), int(max_iters), float(rtol), _p(rr))
+        if it < 0:
+            raise ValueError("map_cg needs the quadratic prior")
+        return x, int(it), float(rr[0])
 
     def centralized_icd(self, x0=None, max_passes=100000, rtol=1e-14, mode=MODE_EXACT):
         x = np.zeros(self.n) if x0 is None else np.array(x0, dtype=np.float64)

@@ -517,6 +517,121 @@ int orc_centralized_icd(const orc_state* S, double* x, int max_passes, double rt
   return it;
 }
 
+/* ---------------- MAP of the quadratic prior by conjugate gradients ------ */
+
+/* out = H v with H = A^T Lambda A + L_b / sigma_x^2, the Hessian of f for the
+ * quadratic prior (eq. (global_obj) with rho(d) = d^2 / (2 sigma_x^2)); L_b is
+ * the weighted graph Laplacian of the 8-neighbour cliques: (L_b v)_s =
+ * sum_r b_sr (v_s - v_r).  tmp: scratch of n_rows doubles. */
+static void quad_hessian_apply(const orc_state* S, const double* v, double* out, double* tmp) {
+  /* tmp = A v, agent by agent (the agents' rows are disjoint) */
+#pragma omp parallel for schedule(static, 1)
+  for (int a = 0; a < S->N; ++a) {
+    for (int64_t r = 0; r < S->n_rows; ++r)
+      if (S->row_agent[r] == a) tmp[r] = 0.0;
+    for (int64_t s = 0; s < S->n; ++s)
+      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t) tmp[S->rw[a][t]] += S->av[a][t] * v[s];
+  }
+  const double c = 1.0 / (S->sx * S->sx);
+#pragma omp parallel for schedule(static)
+  for (int64_t s = 0; s < S->n; ++s) {
+    double acc = 0.0;
+    for (int a = 0; a < S->N; ++a)
+      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t) {
+        int32_t r = S->rw[a][t];
+        acc += S->av[a][t] * S->lam[r] * tmp[r];
+      }
+    int64_t nb[8];
+    double wt[8];
+    int k = neighbours(S, s, nb, wt);
+    for (int q = 0; q < k; ++q) acc += c * wt[q] * (v[s] - v[nb[q]]);
+    out[s] = acc;
+  }
+}
+
+/*
+ * MAP estimate for the quadratic prior: solves the normal equations
+ *   (A^T Lambda A + L_b / sigma_x^2) x = A^T Lambda y
+ * by conjugate gradients with the diagonal of the matrix as preconditioner
+ * (Jacobi-preconditioned CG, textbook form), from x (in/out), until
+ * ||b - H x|| <= rtol ||b||.  Requires the quadratic prior (kind 0).  Returns
+ * the iterations done (-1 if the prior is not quadratic); *relres receives
+ * the final ||b - H x|| / ||b||.
+ */
+int orc_map_cg(const orc_state* S, double* x, int max_iters, double rtol, double* relres) {
+  if (S->kind != 0) return -1;
+  const int64_t n = S->n;
+  double* b = (double*)calloc(n, sizeof(double));
+  double* r = (double*)malloc(sizeof(double) * n);
+  double* z = (double*)malloc(sizeof(double) * n);
+  double* p = (double*)malloc(sizeof(double) * n);
+  double* q = (double*)malloc(sizeof(double) * n);
+  double* dinv = (double*)malloc(sizeof(double) * n);
+  double* tmp = (double*)malloc(sizeof(double) * S->n_rows);
+  const double c = 1.0 / (S->sx * S->sx);
+  for (int64_t s = 0; s < n; ++s) {
+    double bs = 0.0, ds = 0.0;
+    for (int a = 0; a < S->N; ++a)
+      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t) {
+        int32_t rr = S->rw[a][t];
+        bs += S->av[a][t] * S->lam[rr] * S->y[rr];
+        ds += S->av[a][t] * S->av[a][t] * S->lam[rr];
+      }
+    int64_t nb[8];
+    double wt[8];
+    int k = neighbours(S, s, nb, wt);
+    for (int j = 0; j < k; ++j) ds += c * wt[j];
+    b[s] = bs;
+    dinv[s] = ds > 0 ? 1.0 / ds : 1.0;
+  }
+  double bn = 0.0;
+  for (int64_t s = 0; s < n; ++s) bn += b[s] * b[s];
+  bn = sqrt(bn);
+  quad_hessian_apply(S, x, q, tmp);
+  double rz = 0.0, rn = 0.0;
+  for (int64_t s = 0; s < n; ++s) {
+    r[s] = b[s] - q[s];
+    z[s] = dinv[s] * r[s];
+    p[s] = z[s];
+    rz += r[s] * z[s];
+    rn += r[s] * r[s];
+  }
+  int it = 0;
+  while (it < max_iters && sqrt(rn) > rtol * bn) {
+    quad_hessian_apply(S, p, q, tmp);
+    double pq = 0.0;
+    for (int64_t s = 0; s < n; ++s) pq += p[s] * q[s];
+    if (!(pq > 0)) break;
+    const double alpha = rz / pq;
+    double rz1 = 0.0;
+    rn = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+      x[s] += alpha * p[s];
+      r[s] -= alpha * q[s];
+      z[s] = dinv[s] * r[s];
+      rz1 += r[s] * z[s];
+      rn += r[s] * r[s];
+    }
+    const double beta = rz1 / rz;
+    rz = rz1;
+    for (int64_t s = 0; s < n; ++s) p[s] = z[s] + beta * p[s];
+    ++it;
+  }
+  /* the true residual of the returned x */
+  quad_hessian_apply(S, x, q, tmp);
+  double tn = 0.0;
+  for (int64_t s = 0; s < n; ++s) tn += (b[s] - q[s]) * (b[s] - q[s]);
+  if (relres) *relres = bn > 0 ? sqrt(tn) / bn : sqrt(tn);
+  free(b);
+  free(r);
+  free(z);
+  free(p);
+  free(q);
+  free(dinv);
+  free(tmp);
+  return it;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

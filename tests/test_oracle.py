@@ -149,6 +149,70 @@ def test_P3_fixed_point_invariants(quad32):
     assert np.abs(gsum).max() < 1e-8 * scale
 
 
+def test_P2_conjugate_gradient_map_is_the_dense_map(quad32):
+    """The oracle's CG solve of the normal equations returns the dense
+    Cholesky MAP; its reported residual is the true one."""
+    d = quad32
+    x, it, rel = d["O"].map_cg(rtol=1e-14)
+    assert it > 0 and rel <= 1e-13
+    H = d["A"].T @ (d["lam"][:, None] * d["A"]) + d["Lb"] / d["sx"] ** 2
+    b = d["A"].T @ (d["lam"] * d["y"])
+    assert abs(np.linalg.norm(b - H @ x) / np.linalg.norm(b) - rel) <= 1e-13
+    nrmse = np.linalg.norm(x - d["xmap"]) / np.linalg.norm(d["xmap"])
+    assert nrmse < 1e-11, nrmse
+
+
+def test_P2_conjugate_gradient_map_larger_than_a_dense_solve():
+    """At 48x48 with 72 views (no dense solve here): the CG MAP zeroes the gradient of f (the
+    oracle's gradient routine, checked against finite differences of f in
+    the q-GGMRF test) and equals the centralised exact ICD, an unrelated
+    algorithm, and the MACE fixed point of 3 agents."""
+    g = mi.Geometry(48, 48, 72, 72)
+    sx = 0.002
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, 31)
+    va = mi.interleaved_partition(g.n_views, 3)
+    O = oracle.Oracle(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, s.y, s.lam, va, 0, sx)
+    x, it, rel = O.map_cg(rtol=1e-13)
+    assert rel <= 1e-13
+    g0 = np.abs(O.gradient(np.zeros(g.n))).max()
+    assert np.abs(O.gradient(x)).max() < 1e-10 * g0
+    xc, _ = O.centralized_icd(rtol=1e-15, max_passes=20000)
+    assert np.linalg.norm(xc - x) / np.linalg.norm(x) < 1e-10
+    res = O.mace_solve(0.8, 5e-4, 20000, tol=1e-13)
+    assert res["resid"][-1] < 1e-13
+    assert np.linalg.norm(res["x"] - x) / np.linalg.norm(x) < 1e-10
+
+
+def test_P2_conjugate_gradient_refuses_a_non_quadratic_prior():
+    g = mi.Geometry(8, 8, 12, 12)
+    O, A, lam, y, va = _problem(g, 3, 1, 1, 0.01, 2.0, 1.2, 1.0)
+    with pytest.raises(ValueError):
+        O.map_cg()
+
+
+@pytest.mark.parametrize("kind,relax", [(0, 1.0), (1, 0.5)])
+def test_stopping_statistic_is_the_mann_step_over_two_rho(kind, relax):
+    """Algorithm 1: w^{k+1} - w^k = rho (2 X^{k+1} - v^k) - rho w^k
+    = 2 rho (X^{k+1} - G w^k), since v^k = 2 G w^k - w^k.  So the residual the
+    oracle reports, r_k = ||X^{k+1} - G w^k|| / ||w^k||, must equal
+    ||w^{k+1} - w^k|| / (2 rho ||w^k||) computed from the iterates w the oracle
+    returns after k and k + 1 iterations (k >= 1, where w^k != 0)."""
+    g = mi.Geometry(16, 16, 24, 24)
+    N, rho, sigma = 3, 0.7, 0.002
+    O, A, lam, y, va = _problem(g, 41, N, kind, 0.002, 2.0, 1.2, 1.0)
+    K = 6
+    full = O.mace_solve(rho, sigma, K, relax=relax)
+    ws = [O.mace_solve(rho, sigma, k, relax=relax)["w"] for k in range(1, K + 1)]
+    for k in range(1, K):
+        step = np.linalg.norm(ws[k] - ws[k - 1]) / (2 * rho * np.linalg.norm(ws[k - 1]))
+        assert abs(full["resid"][k] - step) <= 1e-12 * step, (k, full["resid"][k], step)
+    # k = 0: w^0 = 0, and the statistic's denominator is ||X^1||
+    X1 = O.mace_solve(rho, sigma, 1, relax=relax)["X"]
+    num = np.linalg.norm(ws[0]) / (2 * rho)
+    assert abs(full["resid"][0] - num / np.linalg.norm(X1)) <= 1e-12 * full["resid"][0]
+
+
 def test_P2_qggmrf_fixed_point_matches_centralised_icd():
     g = mi.Geometry(24, 24, 48, 36)
     N, sx, sigma = 2, 0.001, 0.001
