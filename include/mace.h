@@ -90,12 +90,15 @@ typedef struct {
                              per colour); 1 = sequential (one super-voxel of
                              an agent at a time: the visiting order of
                              mace_visit_order) */
-  int32_t fp32_tail_iters;/* with precision 1: the last this many of the
-                             max_iters iterations of mace_solve /
-                             mace_solve_batch run with FP32 A (after an
-                             e-refresh with FP32 A); a scan that meets tol
-                             earlier stops in FP16, and the server, whose
-                             scans stop on tol, runs FP16 throughout */
+  int32_t fp32_tail_iters;/* with precision 1 (> 0: the FP32 values are
+                             kept too): a scan switches to the FP32 values
+                             when it first meets tol with the FP16 ones, or
+                             this many iterations before max_iters, which
+                             ever comes first; theta2 and e = y - A X_i are
+                             rebuilt with the FP32 values at the switch, and
+                             the scan then runs until it meets tol again (or
+                             max_iters).  Applies to mace_solve,
+                             mace_solve_batch and served scans. */
   int64_t hbm_budget_bytes; /* 0 = no limit */
   int32_t refresh_every;  /* recompute e = y - A X_i every this many Mann
                              iterations to stop FP32 drift (0 = never) */
@@ -109,6 +112,8 @@ typedef struct {
   double sweep_ms;  /* with timing on: time of the ICD sweep launches (HIP events) */
   int32_t sweep_launches; /* number of sweep launches timed */
   double iter_ms;   /* with timing on: time of all Mann iterations (HIP events) */
+  int32_t fp32_tail_iters; /* precision 1 with an FP32 tail: iterations run
+                              with the FP32 values after the switch */
 } mace_info;
 
 /*
@@ -355,6 +360,14 @@ void mace_server_destroy(mace_server* srv);
 
 void mace_free_system(mace_system* sys);
 const char* mace_last_error(void);
+
+/* Testing hook (not part of the method): the after-th next device
+ * allocation of the library in this process (0 = the very next one) fails as
+ * if the device were out of memory; after < 0 switches the hook off.  It
+ * fires once.  Used to check that a call which fails on memory leaves its
+ * system usable: the next call allocates again (or fails cleanly) and never
+ * launches a kernel on a buffer that was not allocated. */
+int mace_test_fail_alloc(int32_t after);
 
 #ifdef __cplusplus
 }

@@ -53,7 +53,7 @@ class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("residual", ctypes.c_double),
                 ("equits", ctypes.c_double), ("status", ctypes.c_int32),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
-                ("iter_ms", ctypes.c_double)]
+                ("iter_ms", ctypes.c_double), ("fp32_tail_iters", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -122,6 +122,8 @@ def _load():
     L.mace_get_config.restype = ctypes.c_int
     L.mace_free_system.argtypes = [vp]
     L.mace_free_system.restype = None
+    L.mace_test_fail_alloc.argtypes = [i32]
+    L.mace_test_fail_alloc.restype = ctypes.c_int
     L.mace_last_error.argtypes = []
     L.mace_last_error.restype = ctypes.c_char_p
     return L
@@ -136,11 +138,16 @@ EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_pnp", "mace_solve_dev"
             "mace_check_layout", "mace_set_timing", "mace_set_relaxation", "mace_server_create",
             "mace_server_submit", "mace_server_wait", "mace_server_stats", "mace_server_destroy",
             "mace_autotune", "mace_get_config",
-            "mace_free_system", "mace_last_error")
+            "mace_free_system", "mace_last_error", "mace_test_fail_alloc")
 
 
 def last_error() -> str:
     return _lib.mace_last_error().decode()
+
+
+def test_fail_alloc(after: int) -> None:
+    """Testing hook: make the after-th next device allocation fail (-1: off)."""
+    _lib.mace_test_fail_alloc(int(after))
 
 
 def _check(rc, allow=(MACE_OK, MACE_W_MAXITER)):

@@ -31,6 +31,11 @@ int fail(int code, const char* fmt, ...) {
 }
 const std::string& last_error_text() { return g_err; }
 
+std::atomic<int>& alloc_fail_countdown() {
+  static std::atomic<int> c{-1};
+  return c;
+}
+
 std::mutex& capture_mutex() {
   static std::mutex mu;
   return mu;
@@ -38,6 +43,11 @@ std::mutex& capture_mutex() {
 }  // namespace mace
 
 extern "C" const char* mace_last_error(void) { return g_err.c_str(); }
+
+extern "C" int mace_test_fail_alloc(int32_t after) {
+  alloc_fail_countdown().store(after < 0 ? -1 : after);
+  return MACE_OK;
+}
 
 mace_system::~mace_system() {
   batch.graphs.clear();

@@ -45,6 +45,8 @@ struct SlotDesc {
   int* counter;       // [0] Mann iterations done, [1] epilogue ticket (0 between launches)
   int resid_cap;
   int active;         // 0: the slot's tasks and epilogue are skipped
+  int prec;           // matrix values the slot's sweeps read: 0 FP32, 1 FP16
+                      // (a sweep launch runs only the slots of its precision)
 };
 
 struct SvArgs {

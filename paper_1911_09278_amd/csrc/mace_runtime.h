@@ -3,6 +3,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -14,6 +15,18 @@
 #include "mace_internal.h"
 
 namespace mace {
+
+// Allocation-failure hook for tests: when the countdown is k >= 0, the k-th
+// next device allocation (0 = the next one) fails with hipErrorOutOfMemory.
+std::atomic<int>& alloc_fail_countdown();
+inline bool alloc_should_fail() {
+  std::atomic<int>& c = alloc_fail_countdown();
+  int v = c.load();
+  while (v >= 0) {
+    if (c.compare_exchange_weak(v, v - 1)) return v == 0;
+  }
+  return false;
+}
 
 // Records the calling thread's error message and returns code.
 int fail(int code, const char* fmt, ...);
@@ -48,12 +61,19 @@ struct DevBuf {
     p = nullptr;
     count = 0;
   }
+  // On failure the buffer stays empty (p == nullptr, count == 0), so a later
+  // size check sees it as missing and allocates again.
   hipError_t alloc(size_t n) {
     reset();
-    count = n;
     if (n == 0) return hipSuccess;
     std::lock_guard<std::mutex> lk(capture_mutex());
-    return hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
+    if (alloc_should_fail()) return hipErrorOutOfMemory;
+    T* q = nullptr;
+    const hipError_t e = hipMalloc(reinterpret_cast<void**>(&q), n * sizeof(T));
+    if (e != hipSuccess) return e;
+    p = q;
+    count = n;
+    return hipSuccess;
   }
   hipError_t upload(const T* h, size_t n) {
     hipError_t e = alloc(n);
@@ -154,11 +174,16 @@ int64_t slot_bytes(const mace_system* s, int resid_cap);
 int ensure_slot(mace_system* s, Batch& b, int idx, int resid_cap);
 void release_slot(Batch& b, int idx);
 // Writes the device table entry of slot i (stream-ordered, by a kernel).
-int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st);
+// prec: the matrix values the slot reads (-1: the system's precision).
+int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st, int prec = -1);
 int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam,
                const float* w_init, const SvArgs& base, hipStream_t st);
 int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, const SvArgs& base,
-                  bool theta2, hipStream_t st);
+                  hipStream_t st);
+// Switches slot i to the FP32 matrix values (theta2 and e rebuilt with them).
+int switch_slot_fp32(mace_system* s, Batch& b, int i, const SvArgs& base, hipStream_t st);
+// Bit p set when an active slot among the first n_slots reads precision p.
+int slot_prec_mask(const Batch& b, int n_slots);
 // One Mann iteration; through a captured graph when use_graph (the batch
 // solve), eager launches otherwise (the server's worker threads).
 int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, const SvArgs& a,

@@ -51,6 +51,7 @@ struct Group {
   Batch batch;
   std::vector<Request*> req;  // per slot; nullptr = free
   std::vector<int> iters;
+  std::vector<int> tail_iters;  // iterations run with the FP32 values after the switch
   std::vector<int64_t> bytes;  // device bytes held by each slot (0 = none)
   int ticks = 0;
   DevBuf<float> yin, lin;   // staging of admitted scans' y and Lambda
@@ -66,9 +67,14 @@ struct Group {
     for (auto* r : req) k += r != nullptr;
     return k;
   }
+  // field by field: the struct's padding bytes are whatever the caller's
+  // copy held
   bool same(const Request& r) const {
-    return rho == r.rho && sigma == r.sigma && sweeps == r.sweeps &&
-           std::memcmp(&prior, &r.prior, sizeof prior) == 0;
+    const mace_prior& a = prior;
+    const mace_prior& b = r.prior;
+    return rho == r.rho && sigma == r.sigma && sweeps == r.sweeps && a.kind == b.kind &&
+           a.sigma_x == b.sigma_x && a.p == b.p && a.q == b.q && a.T == b.T &&
+           a.b_edge == b.b_edge && a.b_diag == b.b_diag;
   }
 };
 
@@ -120,6 +126,7 @@ std::pair<Group*, int> place(mace_server* sv, int k, const Request& r) {
   if ((int)g->req.size() < kGroupSlots) {
     g->req.push_back(nullptr);
     g->iters.push_back(0);
+    g->tail_iters.push_back(0);
     g->bytes.push_back(0);
     return {g, (int)g->req.size() - 1};
   }
@@ -135,6 +142,7 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
   mace_system* s = sys[k];
   hipStream_t st = s->stream;
   const bool fp16 = s->precision == 1;
+  const bool tail = fp16 && s->fp32_tail > 0;
   for (auto& [g, i] : admitted) {
     Request* r = g->req[i];
     if (!g->hlast) {
@@ -159,6 +167,7 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
     rc = start_slot(s, g->batch, i, g->yin.p, g->lin.p, nullptr, a, st);
     if (rc) return rc;
     g->iters[i] = 0;
+    g->tail_iters[i] = 0;
   }
   std::vector<Group*> ran;
   for (auto& gp : groups[k]) {
@@ -175,7 +184,7 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
     fill_args(s, a, &g->prior, g->rho, g->sigma, fp16);
     a.strict = P == 1 ? 1 : 0;
     if (s->refresh_every > 0 && g->ticks > 0 && g->ticks % s->refresh_every == 0) {
-      int rc = refresh_slots(s, g->batch, n_occ, sch, a, false, st);
+      int rc = refresh_slots(s, g->batch, n_occ, sch, a, st);
       if (rc) return rc;
     }
     // eager launches: a worker thread captures no graph (see capture_mutex)
@@ -194,6 +203,8 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
       Request* r = g->req[i];
       if (!r) continue;
       const int it = ++g->iters[i];
+      const bool in16 = g->batch.htable[i].prec == 1;
+      if (tail && !in16) ++g->tail_iters[i];
       const double res = g->hlast[i];
       int status = -100;
       if (!std::isfinite(res))
@@ -202,6 +213,16 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
         status = MACE_OK;
       else if (it >= r->max_iters)
         status = r->tol > 0 ? MACE_W_MAXITER : MACE_OK;
+      // an FP16 scan with an FP32 tail: it switches to the FP32 values when
+      // it first meets tol, or fp32_tail iterations before max_iters
+      if (tail && in16 && it < r->max_iters &&
+          (status == MACE_OK || (status == -100 && it >= r->max_iters - s->fp32_tail))) {
+        SvArgs a;
+        fill_args(s, a, &g->prior, g->rho, g->sigma, false);
+        int rc = switch_slot_fp32(s, g->batch, i, a, st);
+        if (rc) return rc;
+        continue;
+      }
       if (status == -100) continue;
       r->x.resize(s->n);
       HIP_OK(hipMemcpyAsync(r->x.data(), g->batch.scan[i]->wbar.p, sizeof(float) * s->n,
@@ -212,6 +233,7 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
       r->info.iters = it;
       r->info.residual = res;
       r->info.equits = (double)g->sweeps * it;
+      r->info.fp32_tail_iters = g->tail_iters[i];
       r->info.status = status;
       fin.emplace_back(g, i);
     }

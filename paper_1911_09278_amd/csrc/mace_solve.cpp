@@ -30,23 +30,40 @@ int ensure_slot(mace_system* s, Batch& b, int idx, int resid_cap) {
   ScanSlot& q = *b.scan[idx];
   const size_t nimg = (size_t)s->N * s->n;
   const size_t nrow = (size_t)s->N * s->estride;
-  if (q.e.count != nrow) {
-    HIP_OK(q.e.alloc(nrow));
-    HIP_OK(q.lam.alloc(nrow));
-    HIP_OK(q.yb.alloc(nrow));
-    HIP_OK(q.X.alloc(nimg));
-    HIP_OK(q.w.alloc(nimg));
-    HIP_OK(q.th2.alloc(nimg));
-    HIP_OK(q.wbar.alloc(s->n));
-    HIP_OK(q.aux.alloc(s->n));
-    HIP_OK(q.part.alloc((size_t)s->N * s->n_sv * 4 + epilogue_scratch_doubles()));
-    HIP_OK(q.counter.alloc(2));
-    HIP_OK(hipMemset(q.counter.p, 0, 2 * sizeof(int)));  // the epilogue ticket starts at 0
-  }
-  const int cap = std::max(1, resid_cap);
-  if (q.resid_cap < cap) {
-    HIP_OK(q.resid.alloc((size_t)cap));
-    q.resid_cap = cap;
+  const size_t npart = (size_t)s->N * s->n_sv * 4 + epilogue_scratch_doubles();
+  // Any buffer missing or of the wrong size (a previous call may have failed
+  // half way): the whole slot is allocated again.  On a failure the slot is
+  // left empty, so no table entry can point at a missing buffer.
+  const bool whole = q.e.count == nrow && q.lam.count == nrow && q.yb.count == nrow &&
+                     q.X.count == nimg && q.w.count == nimg && q.th2.count == nimg &&
+                     q.wbar.count == (size_t)s->n && q.aux.count == (size_t)s->n &&
+                     q.part.count == npart && q.counter.count == 2;
+  auto fill = [&]() -> int {
+    if (!whole) {
+      HIP_OK(q.e.alloc(nrow));
+      HIP_OK(q.lam.alloc(nrow));
+      HIP_OK(q.yb.alloc(nrow));
+      HIP_OK(q.X.alloc(nimg));
+      HIP_OK(q.w.alloc(nimg));
+      HIP_OK(q.th2.alloc(nimg));
+      HIP_OK(q.wbar.alloc(s->n));
+      HIP_OK(q.aux.alloc(s->n));
+      HIP_OK(q.part.alloc(npart));
+      HIP_OK(q.counter.alloc(2));
+      HIP_OK(hipMemset(q.counter.p, 0, 2 * sizeof(int)));  // the epilogue ticket starts at 0
+    }
+    const int cap = std::max(1, resid_cap);
+    if (q.resid_cap < cap || !q.resid.p) {
+      q.resid_cap = 0;
+      HIP_OK(q.resid.alloc((size_t)cap));
+      q.resid_cap = cap;
+    }
+    return MACE_OK;
+  };
+  const int rc = fill();
+  if (rc) {
+    release_slot(b, idx);
+    return rc;
   }
   // allocated once at the maximum size: captured graphs hold these addresses
   if (b.lastres.count < (size_t)kMaxScanSlots) HIP_OK(b.lastres.alloc(kMaxScanSlots));
@@ -62,8 +79,7 @@ void release_slot(Batch& b, int idx) {
   if (idx < (int)b.scan.size()) b.scan[idx] = std::make_unique<ScanSlot>();
 }
 
-int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st) {
-  (void)s;
+int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st, int prec) {
   SlotDesc d{};
   if (active) {
     ScanSlot& q = *b.scan[i];
@@ -80,6 +96,7 @@ int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st) {
     d.counter = q.counter.p;
     d.resid_cap = q.resid_cap;
     d.active = 1;
+    d.prec = prec >= 0 ? prec : (s->precision == 1 ? 1 : 0);
   }
   b.htable[i] = d;
   HIP_OK(launch_write_slot(b.table.p, i, d, st));
@@ -106,9 +123,13 @@ int launch_phases(mace_system* s, const Schedule* sch, SvArgs a, int mode, hipSt
 }
 
 // The launches of one Mann iteration: `sweeps` ICD passes (the last one with
-// the reflection + Mann update) and the epilogue.
+// the reflection + Mann update) and the epilogue.  prec_mask says which
+// record precisions the active slots read (bit 0: FP32, bit 1: FP16); each
+// colour phase runs one launch per precision present, each launch only the
+// slots of its precision (the scans are independent, so their order within
+// a phase does not matter).
 int enqueue_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, SvArgs a,
-                      int sweeps, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                      int sweeps, int prec_mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad);
   a.R = sch->R;
   a.slots = b.table.p;
@@ -118,7 +139,11 @@ int enqueue_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots
     for (int c = 0; c < 4; ++c) {
       a.tasks = sch->tasks[c].p;
       a.T = sch->T[c];
-      HIP_OK(launch_sv(a, kSweep, s->slots, sch->grid, lds, st));
+      for (int pr = 0; pr < 2; ++pr) {
+        if (!(prec_mask & (1 << pr))) continue;
+        a.fp16 = pr;
+        HIP_OK(launch_sv(a, kSweep, s->slots, sch->grid, lds, st));
+      }
     }
   }
   if (ev1) HIP_OK(hipEventRecord(ev1, st));
@@ -136,7 +161,6 @@ uint64_t args_key(const SvArgs& a) {
   mix(&a.kind, sizeof a.kind);
   mix(&a.invN, sizeof(float) * 4);  // invN, is2, rho, relax
   mix(&a.bedge, sizeof(float) * 6);
-  mix(&a.fp16, sizeof a.fp16);
   mix(&a.strict, sizeof a.strict);
   mix(&a.hpass, sizeof a.hpass);
   return h;
@@ -173,6 +197,7 @@ int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam
   if (!one) return fail(MACE_E_HIP, "schedule upload failed");
   SvArgs a = base;
   a.strict = P == 1 ? 1 : 0;
+  a.fp16 = b.htable[i].prec;
   rc = launch_phases(s, one, a, kTheta2, st, b.table.p + i);
   if (rc) return rc;
   if (w_init) {
@@ -182,20 +207,53 @@ int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam
   return MACE_OK;
 }
 
-// e = y - A X for every active slot (FP32 drift), and theta2 too when the
-// matrix values change precision.
+// e = y - A X for every active slot (FP32 drift), each slot with the matrix
+// values of its own precision.
 int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, const SvArgs& base,
-                  bool theta2, hipStream_t st) {
+                  hipStream_t st) {
+  int mask = 0;
   for (int i = 0; i < n_slots; ++i) {
     if (!b.htable[i].active) continue;
     ScanSlot& q = *b.scan[i];
     HIP_OK(launch_copy(q.e.p, q.yb.p, (int64_t)s->N * s->estride, st));
+    mask |= 1 << b.htable[i].prec;
   }
-  if (theta2) {
-    int rc = launch_phases(s, sch, base, kTheta2, st, b.table.p);
+  for (int pr = 0; pr < 2; ++pr) {
+    if (!(mask & (1 << pr))) continue;
+    SvArgs a = base;
+    a.fp16 = pr;
+    int rc = launch_phases(s, sch, a, kRefresh, st, b.table.p);
     if (rc) return rc;
   }
-  return launch_phases(s, sch, base, kRefresh, st, b.table.p);
+  return MACE_OK;
+}
+
+// The precision switch of an FP16 scan (slot i): from here on its sweeps read
+// the FP32 matrix values; theta2 and e = y - A X_i are rebuilt with them, so
+// the FP32 iterations start from the exact error sinogram of the current
+// state.  Only slot i is touched (one-slot schedule seeing the table from
+// slot i on).
+int switch_slot_fp32(mace_system* s, Batch& b, int i, const SvArgs& base, hipStream_t st) {
+  int rc = write_slot(s, b, i, 1, st, 0);
+  if (rc) return rc;
+  ScanSlot& q = *b.scan[i];
+  HIP_OK(launch_copy(q.e.p, q.yb.p, (int64_t)s->N * s->estride, st));
+  const int P = default_rows_per_agent(s);
+  Schedule* one = get_schedule(s, 1, -1, P);
+  if (!one) return fail(MACE_E_HIP, "schedule upload failed");
+  SvArgs a = base;
+  a.fp16 = 0;
+  a.strict = P == 1 ? 1 : 0;
+  rc = launch_phases(s, one, a, kTheta2, st, b.table.p + i);
+  if (rc) return rc;
+  return launch_phases(s, one, a, kRefresh, st, b.table.p + i);
+}
+
+int slot_prec_mask(const Batch& b, int n_slots) {
+  int mask = 0;
+  for (int i = 0; i < n_slots; ++i)
+    if (b.htable[i].active) mask |= 1 << b.htable[i].prec;
+  return mask;
 }
 
 // One Mann iteration through a captured graph.  The first iteration with a
@@ -203,12 +261,14 @@ int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, co
 // attribute set-up, which stays out of the capture); the second captures.
 int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, const SvArgs& a,
                   int sweeps, int P, hipStream_t st, bool use_graph) {
-  if (!use_graph) return enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
-  const auto key = std::make_tuple(n_slots, P, sweeps, a.fp16, args_key(a));
+  const int mask = slot_prec_mask(b, n_slots);
+  if (!use_graph)
+    return enqueue_iteration(s, b, sch, n_slots, a, sweeps, mask, st, nullptr, nullptr);
+  const auto key = std::make_tuple(n_slots, P, sweeps, mask, args_key(a));
   auto it = b.graphs.find(key);
   if (it == b.graphs.end()) {
     b.graphs[key] = nullptr;
-    return enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
+    return enqueue_iteration(s, b, sch, n_slots, a, sweeps, mask, st, nullptr, nullptr);
   }
   if (!it->second) {
     auto ng = std::make_unique<IterGraph>();
@@ -218,7 +278,7 @@ int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, co
     {
       std::lock_guard<std::mutex> lk(capture_mutex());
       HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      rc = enqueue_iteration(s, b, sch, n_slots, a, sweeps, st, nullptr, nullptr);
+      rc = enqueue_iteration(s, b, sch, n_slots, a, sweeps, mask, st, nullptr, nullptr);
       e = hipStreamEndCapture(st, &graph);
     }
     ng->graph = graph;  // destroyed with ng on every return below
@@ -313,35 +373,50 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
     for (auto& e : s->ev) HIP_OK(hipEventCreate(&e));
   }
   if (timing) HIP_OK(hipEventRecord(s->ev[2 * max_iters], st));
-  std::vector<int> iters(n, 0), status(n, MACE_OK);
+  std::vector<int> iters(n, 0), status(n, MACE_OK), tail_iters(n, 0);
   std::vector<double> last(n, 0.0);
+  // FP16 scans with an FP32 tail switch to the FP32 values when they first
+  // meet tol, or fp32_tail iterations before max_iters; they stop when they
+  // meet tol again in FP32 (or at max_iters).
+  const bool tail = fp16 && s->fp32_tail > 0;
+  const int tail_at = std::max(0, max_iters - s->fp32_tail);
   int live = n, it = 0;
-  bool tail_done = false;
   for (; it < max_iters && live > 0; ++it) {
-    const bool tail = fp16 && s->fp32_tail > 0 && it >= max_iters - s->fp32_tail;
-    if (tail && !tail_done) {
-      // switch to FP32 values: rebuild e = y - A X and theta2 with them
-      a.fp16 = 0;
-      tail_done = true;
-      rc = refresh_slots(s, b, n, sch, a, true, st);
-      if (rc) return rc;
-    } else if (s->refresh_every > 0 && it > 0 && it % s->refresh_every == 0) {
-      rc = refresh_slots(s, b, n, sch, a, false, st);
+    if (tail && it >= tail_at)
+      for (int i = 0; i < n; ++i)
+        if (b.htable[i].active && b.htable[i].prec == 1) {
+          rc = switch_slot_fp32(s, b, i, a, st);
+          if (rc) return rc;
+        }
+    if (s->refresh_every > 0 && it > 0 && it % s->refresh_every == 0) {
+      rc = refresh_slots(s, b, n, sch, a, st);
       if (rc) return rc;
     }
     if (timing)
-      rc = enqueue_iteration(s, b, sch, n, a, sweeps, st, s->ev[2 * it], s->ev[2 * it + 1]);
+      rc = enqueue_iteration(s, b, sch, n, a, sweeps, slot_prec_mask(b, n), st, s->ev[2 * it],
+                             s->ev[2 * it + 1]);
     else
       rc = run_iteration(s, b, sch, n, a, sweeps, P, st);
     if (rc) return rc;
     for (int i = 0; i < n; ++i)
-      if (b.htable[i].active) iters[i] = it + 1;
+      if (b.htable[i].active) {
+        iters[i] = it + 1;
+        if (tail && b.htable[i].prec == 0) ++tail_iters[i];
+      }
     if (tol > 0) {
       HIP_OK(hipMemcpyAsync(last.data(), b.lastres.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
       for (int i = 0; i < n; ++i) {
         if (!b.htable[i].active) continue;
         const bool bad = !std::isfinite(last[i]);
+        if (!bad && last[i] < tol && tail && b.htable[i].prec == 1) {
+          // met tol with the FP16 values: continue with the FP32 ones
+          if (it + 1 < max_iters) {
+            rc = switch_slot_fp32(s, b, i, a, st);
+            if (rc) return rc;
+          }
+          continue;
+        }
         if (bad || last[i] < tol) {
           if (bad) status[i] = MACE_E_NONFINITE;
           rc = write_slot(s, b, i, 0, st);
@@ -381,6 +456,7 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
       io[i].info->sweep_ms = sweep_ms;
       io[i].info->sweep_launches = timing ? it * sweeps * 4 : 0;
       io[i].info->iter_ms = iter_ms;
+      io[i].info->fp32_tail_iters = tail_iters[i];
     }
     if (status[i] == MACE_E_NONFINITE) worst = MACE_E_NONFINITE;
     else if (status[i] == MACE_W_MAXITER && worst == MACE_OK) worst = MACE_W_MAXITER;

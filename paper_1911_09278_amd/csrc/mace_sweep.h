@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
     h.wbar = glb(sd->wbar);
     h.th2 = glb(sd->th2);
     h.part = glb(sd->part);
-    if (sd->active) h.task = task;
+    if (sd->active && sd->prec == (F16 ? 1 : 0)) h.task = task;
   };
   // Stage task h in LDS: its band (e, Lambda) with the 16 lanes on
   // consecutive channels of one view at a time, the halo tile of the agent
