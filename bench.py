@@ -90,6 +90,216 @@ def cpu_baseline(g, cp, row, val, scan, va, w8, sigma, budget_s=50.0):
                       f"({upd} agent-voxel updates, {dt:.1f} s)"}
 
 
+def host_info():
+    """CPU model, RAM and hardware threads of this host (for the CPU baseline)."""
+    model, ram = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = int(line.split()[1]) * 1024
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "ram_bytes": ram, "host_threads": os.cpu_count()}
+
+
+def leg_slices(sysm, w8, m, mi, torch, sigma, iters, n_slices=64):
+    """Batched slices (64 independent 512x512 slices, each its own phantom,
+    sharing the loaded scan512 system): all slices advance together through
+    mace_solve_batch_dev, against the same slices solved one at a time with
+    mace_solve_dev, both for `iters` Mann iterations."""
+    g = w8.geom
+    dev = torch.device("cuda:0")
+    log(f"slices: {n_slices} scans")
+    ys, ls, xs = [], [], []
+    for i in range(n_slices):
+        sc = mi.scan(g, mi.WORKLOADS["slices512"].seed + i)
+        ys.append(torch.from_numpy(sc.y).to(dev))
+        ls.append(torch.from_numpy(sc.lam).to(dev))
+        xs.append(torch.empty(g.n, dtype=torch.float32, device=dev))
+    prior = m.make_prior(w8.prior_kind, w8.sigma_x, w8.p, w8.q, w8.T)
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    yp, lp, xp = ([t.data_ptr() for t in v] for v in (ys, ls, xs))
+    log("slices: batched")
+    sysm.solve_batch_dev(yp, lp, prior, w8.rho, sigma, iters, xp, stream_ptr=sp)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info_b = sysm.solve_batch_dev(yp, lp, prior, w8.rho, sigma, iters, xp, stream_ptr=sp)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    xb = torch.stack(xs).cpu().numpy()
+    log("slices: one at a time")
+    t0 = time.perf_counter()
+    info_s = [sysm.solve_dev(yp[i], lp[i], prior, w8.rho, sigma, iters, xp[i], stream_ptr=sp)
+              for i in range(n_slices)]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    x1 = torch.stack(xs).cpu().numpy()
+    nnz = sysm.nnz
+    rows = g.n_views * g.n_channels
+    hbm_floor_ms = (nnz * 8 + n_slices * (w8.n_agents * g.n * 20 + rows * 12)) / 8e12 * 1e3
+    return {"workload": f"slices512: {n_slices} slices 512x512, 720 views, 736 channels, "
+                        "16 agents, one shared matrix", "mann_iters": iters, "sigma": sigma,
+            "slices_per_s_batched": n_slices / tb, "slices_per_s_one_at_a_time": n_slices / ts,
+            "speedup": ts / tb, "ms_per_mann_iter_batched": tb / iters * 1e3,
+            "hbm_floor_ms_per_mann_iter": hbm_floor_ms,
+            "mean_residual_batched": float(np.mean([i.residual for i in info_b])),
+            "mean_residual_one_at_a_time": float(np.mean([i.residual for i in info_s])),
+            "nrmse_batched_vs_one_at_a_time":
+                float(np.sqrt(((xb - x1) ** 2).sum() / (x1 ** 2).sum()))}
+
+
+def leg_fp16(m, mi, torch, iters=60):
+    """1024x1024, 1440 views, 1472 channels, 32 agents (q-GGMRF): FP16 matrix
+    values with a per agent-pixel scale, FP16 throughout and with the last 5
+    Mann iterations on the FP32 values, against all-FP32; `iters` Mann
+    iterations each.  The FP16 sweep launch is priced against the roofline
+    of FP16 values + 16-bit rows (4 B per nonzero) plus the state bytes."""
+    w = mi.WORKLOADS["scan1024"]
+    g = w.geom
+    sigma = 5e-5
+    log("fp16: 1024x1024 matrix")
+    cp, row, val = mi.system_matrix(g)
+    sc = mi.scan(g, w.seed)
+    nnz = int(cp[-1])
+    prior = m.make_prior(w.prior_kind, w.sigma_x, w.p, w.q, w.T)
+    dev = torch.device("cuda:0")
+    y = torch.from_numpy(sc.y).to(dev)
+    lam = torch.from_numpy(sc.lam).to(dev)
+    x = torch.empty(g.n, dtype=torch.float32, device=dev)
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    out = {"workload": "scan1024: 1024x1024, 1440 views, 1472 channels, 32 agents, "
+                       "q-GGMRF p=2 q=1.2 T=1 sigma_x=0.01, rho=0.8",
+           "mann_iters": iters, "sigma": sigma, "nnz": nnz}
+    xs = {}
+    for prec in (0, 1):
+        log(f"fp16: loading precision {prec}")
+        t = time.perf_counter()
+        sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents,
+                        precision=prec, fp32_tail_iters=5 if prec else 0)
+        log(f"fp16: loaded in {time.perf_counter() - t:.1f} s")
+        sysm.set_relaxation(0.5)
+        runs = (("fp32", 0),) if prec == 0 else (("fp16", 0), ("fp16_tail5", 5))
+        for name, tail in runs:
+            if prec:
+                sysm.set_fp32_tail(tail)
+            sysm.solve_dev(y.data_ptr(), lam.data_ptr(), prior, w.rho, sigma, iters,
+                           x.data_ptr(), stream_ptr=sp)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = sysm.solve_dev(y.data_ptr(), lam.data_ptr(), prior, w.rho, sigma, iters,
+                                  x.data_ptr(), stream_ptr=sp)
+            dt = time.perf_counter() - t0
+            xs[name] = x.cpu().numpy().astype(np.float64)
+            sysm.set_timing(True)
+            ti = sysm.solve_dev(y.data_ptr(), lam.data_ptr(), prior, w.rho, sigma, iters,
+                                x.data_ptr(), stream_ptr=sp)
+            sysm.set_timing(False)
+            out[name] = {"voxel_updates_per_s": iters * w.n_agents * g.n / dt,
+                         "ms_per_scan": dt * 1e3, "residual": info.residual,
+                         "sweep_launch_us": ti.sweep_ms * 1e3 / ti.sweep_launches,
+                         "matrix_bytes": sysm.matrix_bytes}
+        sysm.close()
+    del cp, row, val
+    state = w.n_agents * g.n * 20 + g.n_views * g.n_channels * 12
+    for name, per_nnz in (("fp32", 8), ("fp16", 4)):
+        launch_bytes = (nnz * per_nnz + state) / 4.0
+        ach = launch_bytes / (out[name]["sweep_launch_us"] * 1e-6) / 1e9
+        out[name]["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                 "bytes_per_launch": launch_bytes,
+                                 "bytes_per_nnz": per_nnz}
+    ref = xs["fp32"]
+    for name in ("fp16", "fp16_tail5"):
+        out[name]["nrmse_vs_fp32"] = float(np.linalg.norm(xs[name] - ref) / np.linalg.norm(ref))
+    return out
+
+
+def leg_serve(m, mi, torch, n_arrivals=300, tol=1e-4, max_iters=3000):
+    """Served 256x256 scans (360 views, 368 channels, 8 agents, q-GGMRF, each
+    its own phantom) stopping at r < tol: the one-scan-at-a-time FP32 path
+    (mace_solve_dev, one scan after the other), the server's capacity (64
+    scans submitted at once), then Poisson arrivals at 70% of that capacity;
+    latency from submit to result, the first 10% of arrivals dropped as
+    warm-up."""
+    w = mi.WORKLOADS["serve256"]
+    g = w.geom
+    sigma = 2e-4
+    cp, row, val = mi.system_matrix(g)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents)
+    del cp, row, val
+    prior = m.make_prior(w.prior_kind, w.sigma_x, w.p, w.q, w.T)
+    log(f"serve: {n_arrivals + 64} scans")
+    scans = [mi.scan(g, 1916000 + i) for i in range(n_arrivals + 64)]
+    dev = torch.device("cuda:0")
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    n_seq = 32
+    ys = [torch.from_numpy(scans[i].y).to(dev) for i in range(n_seq)]
+    ls = [torch.from_numpy(scans[i].lam).to(dev) for i in range(n_seq)]
+    x = torch.empty(g.n, dtype=torch.float32, device=dev)
+    log("serve: one scan at a time")
+    sysm.solve_dev(ys[0].data_ptr(), ls[0].data_ptr(), prior, w.rho, sigma, max_iters,
+                   x.data_ptr(), tol=tol, stream_ptr=sp)
+    t0 = time.perf_counter()
+    it_seq = []
+    for i in range(n_seq):
+        info = sysm.solve_dev(ys[i].data_ptr(), ls[i].data_ptr(), prior, w.rho, sigma, max_iters,
+                              x.data_ptr(), tol=tol, stream_ptr=sp)
+        it_seq.append(info.iters)
+    seq_rate = n_seq / (time.perf_counter() - t0)
+    srv = m.Server([sysm])
+    log("serve: capacity (64 at once)")
+    t0 = time.perf_counter()
+    tk = [srv.submit(0, scans[n_arrivals + i].y, scans[n_arrivals + i].lam, prior, w.rho, sigma,
+                     tol, max_iters) for i in range(64)]
+    for t in tk:
+        srv.wait(t, g.n)
+    capacity = 64 / (time.perf_counter() - t0)
+    rate = 0.7 * capacity
+    log(f"serve: {n_arrivals} Poisson arrivals at {rate:.1f}/s")
+    rng = np.random.default_rng(1916)
+    gaps = rng.exponential(1.0 / rate, n_arrivals)
+    tickets = []
+    t0 = time.perf_counter()
+    t_next = t0
+    for i in range(n_arrivals):
+        t_next += gaps[i]
+        d = t_next - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        tickets.append(srv.submit(0, scans[i].y, scans[i].lam, prior, w.rho, sigma, tol,
+                                  max_iters))
+    lat, its, ok = [], [], 0
+    for t in tickets:
+        _, info, l = srv.wait(t, g.n)
+        lat.append(l)
+        its.append(info.iters)
+        ok += info.status == m.MACE_OK
+    span = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    sysm.close()
+    kept = lat[n_arrivals // 10:]
+    return {"workload": "serve256: 256x256, 360 views, 368 channels, 8 agents, q-GGMRF "
+                        "p=2 q=1.2 T=1 sigma_x=0.01, rho=0.8, each scan its own phantom",
+            "sigma": sigma, "tol": tol, "arrivals": n_arrivals, "offered_rate": rate,
+            "served_rate": n_arrivals / span, "converged": ok,
+            "latency_p50_ms": float(np.percentile(kept, 50) * 1e3),
+            "latency_p99_ms": float(np.percentile(kept, 99) * 1e3),
+            "mean_iters_served": float(np.mean(its)),
+            "capacity_scans_per_s": capacity,
+            "one_at_a_time_fp32_scans_per_s": seq_rate,
+            "mean_iters_one_at_a_time": float(np.mean(it_seq)),
+            "max_in_flight": st["max_in_flight"]}
+
+
 def _common(metric, value, unit, steps, warmup, ms, dtype, config, higher=True):
     return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak",
@@ -481,6 +691,8 @@ def main():
     ap.add_argument("--sv-size", type=int, default=0)
     ap.add_argument("--relax", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline scan (no slices / FP16 / serving legs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--mode", default="scan", choices=("scan", "slices", "serve", "fp16", "pnp", "study"),
@@ -606,6 +818,14 @@ def main():
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, cp, row, val, scan, va, w8, args.sigma)
+        out["cpu_baseline"].update(host_info())
+    if not args.no_extra:
+        del cp, row, val
+        extra = {"slices": leg_slices(sysm, w8, m, mi, torch, args.sigma, args.iters)}
+        sysm.close()
+        extra["fp16_1024"] = leg_fp16(m, mi, torch, args.iters)
+        extra["serve256"] = leg_serve(m, mi, torch)
+        out["extra"] = extra
     print(json.dumps(out), flush=True)
 
 

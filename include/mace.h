@@ -79,7 +79,8 @@ typedef struct {
 typedef struct {
   int32_t precision;      /* 0: A values FP32 (default); 1: FP16 with a per
                              (agent, pixel) FP32 scale */
-  int32_t sv_size;        /* super-voxel side S in pixels: 4 or 8; 0 = 8 for
+  int32_t sv_size;        /* super-voxel side S in pixels: 4, 8, 16 or 32
+                             (16 and 32: general format); 0 = 8 for
                              images of at least 256 x 256 pixels, else 4;
                              -1 = autotuned with rows_per_agent (see
                              mace_autotune) */
@@ -102,6 +103,14 @@ typedef struct {
   int64_t hbm_budget_bytes; /* 0 = no limit */
   int32_t refresh_every;  /* recompute e = y - A X_i every this many Mann
                              iterations to stop FP32 drift (0 = never) */
+  int32_t format;         /* device record format of the matrix: 0 = the
+                             compact format when the matrix and options
+                             allow it, else the general one; 1 = compact
+                             (sv_size 4 or 8, at most 128 views per agent,
+                             at most two nonzeros per column and view, on
+                             adjacent channels; FP32 or FP16 values);
+                             2 = general (any sparsity pattern and view
+                             count, sv_size 4, 8, 16 or 32, FP32 values) */
 } mace_opts;
 
 typedef struct {
@@ -184,6 +193,7 @@ int mace_solve_dev(mace_system* sys, const float* y, const float* lambda,
                    int32_t max_iters, double tol, const float* w_init, float* x_out,
                    mace_info* info, void* stream);
 
+
 /*
  * Batched partial-update MACE: n_scans independent scans of this geometry
  * (e.g. the slices of a volume, or requests of a reconstruction service)
@@ -253,6 +263,12 @@ int mace_get_error_sinogram(const mace_system* sys, float* e);
  * updated at once.  Applies to later mace_solve / mace_prox calls.
  */
 int mace_set_relaxation(mace_system* sys, double gamma);
+
+/* Precision-path setting of a system loaded with precision 1: the FP32
+ * tail (see mace_opts.fp32_tail_iters) of later solves; 0 runs FP16
+ * throughout.  A positive value needs the FP32 values, which a system holds
+ * when it was loaded with fp32_tail_iters > 0.  Errors: MACE_E_ARG. */
+int mace_set_fp32_tail(mace_system* sys, int32_t iters);
 
 /* Enable (1) or disable (0) HIP-event timing of the solve's kernels; the
  * figures land in mace_info.sweep_ms / sweep_launches / iter_ms. */

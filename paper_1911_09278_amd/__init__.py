@@ -46,7 +46,8 @@ class Prior(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("sv_size", ctypes.c_int32),
                 ("rows_per_agent", ctypes.c_int32), ("fp32_tail_iters", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64), ("refresh_every", ctypes.c_int32)]
+                ("hbm_budget_bytes", ctypes.c_int64), ("refresh_every", ctypes.c_int32),
+                ("format", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -97,6 +98,8 @@ def _load():
     L.mace_get_error_sinogram.restype = ctypes.c_int
     L.mace_set_relaxation.argtypes = [vp, d]
     L.mace_set_relaxation.restype = ctypes.c_int
+    L.mace_set_fp32_tail.argtypes = [vp, i32]
+    L.mace_set_fp32_tail.restype = ctypes.c_int
     L.mace_set_timing.argtypes = [vp, i32]
     L.mace_set_timing.restype = ctypes.c_int
     L.mace_system_bytes.argtypes = [vp]
@@ -138,7 +141,8 @@ EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_pnp", "mace_solve_dev"
             "mace_check_layout", "mace_set_timing", "mace_set_relaxation", "mace_server_create",
             "mace_server_submit", "mace_server_wait", "mace_server_stats", "mace_server_destroy",
             "mace_autotune", "mace_get_config",
-            "mace_free_system", "mace_last_error", "mace_test_fail_alloc")
+            "mace_free_system", "mace_last_error", "mace_test_fail_alloc",
+            "mace_set_fp32_tail")
 
 
 def last_error() -> str:
@@ -166,7 +170,7 @@ def make_prior(kind=0, sigma_x=0.02, p=2.0, q=2.0, T=1.0, b_edge=0.0, b_diag=0.0
 
 
 def check_layout(nx, ny, n_views, n_channels, col_ptr, row, val, n_agents, view_to_agent=None,
-                 precision=0, sv_size=0, rows_per_agent=0, fp32_tail_iters=0) -> int:
+                 precision=0, sv_size=0, rows_per_agent=0, fp32_tail_iters=0, format=0) -> int:
     """Host-only dry run of the device layout and schedules (no GPU needed).
     Returns the LDS bytes per workgroup; raises MaceError on any bad index."""
     cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
@@ -174,7 +178,8 @@ def check_layout(nx, ny, n_views, n_channels, col_ptr, row, val, n_agents, view_
     vl = np.ascontiguousarray(val, dtype=np.float32)
     va = None if view_to_agent is None else np.ascontiguousarray(view_to_agent, dtype=np.int32)
     g = Geom(int(nx), int(ny), int(n_views), int(n_channels))
-    o = Opts(int(precision), int(sv_size), int(rows_per_agent), int(fp32_tail_iters), 0, 0)
+    o = Opts(int(precision), int(sv_size), int(rows_per_agent), int(fp32_tail_iters), 0, 0,
+             int(format))
     lds = ctypes.c_int64(0)
     _check(_lib.mace_check_layout(ctypes.byref(g), _ptr(cp), _ptr(rw), _ptr(vl), int(n_agents),
                                   _ptr(va), ctypes.byref(o), ctypes.byref(lds)))
@@ -210,7 +215,7 @@ class System:
 
     def __init__(self, nx, ny, n_views, n_channels, col_ptr, row, val, n_agents,
                  view_to_agent=None, precision=0, sv_size=0, rows_per_agent=0,
-                 fp32_tail_iters=0, hbm_budget_bytes=0, refresh_every=0):
+                 fp32_tail_iters=0, hbm_budget_bytes=0, refresh_every=0, format=0):
         self._h = None
         cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
         rw = np.ascontiguousarray(row, dtype=np.int32)
@@ -221,8 +226,9 @@ class System:
         self.n = self.nx * self.ny
         self.n_rows = int(n_views) * int(n_channels)
         self.N = int(n_agents)
+        self.nnz = int(cp[-1])
         opts = Opts(int(precision), int(sv_size), int(rows_per_agent), int(fp32_tail_iters),
-                    int(hbm_budget_bytes), int(refresh_every))
+                    int(hbm_budget_bytes), int(refresh_every), int(format))
         h = ctypes.c_void_p()
         _check(_lib.mace_load_system(ctypes.byref(self.geom), _ptr(cp), _ptr(rw), _ptr(vl),
                                      self.N, _ptr(va), ctypes.byref(opts), ctypes.byref(h)))
@@ -350,6 +356,10 @@ class System:
 
     def set_relaxation(self, gamma):
         _check(_lib.mace_set_relaxation(self._h, float(gamma)))
+
+    def set_fp32_tail(self, iters):
+        """FP32 tail of later solves (precision-1 systems; see mace_opts)."""
+        _check(_lib.mace_set_fp32_tail(self._h, int(iters)))
 
     def set_timing(self, enable=True):
         _check(_lib.mace_set_timing(self._h, 1 if enable else 0))

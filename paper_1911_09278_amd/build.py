@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libmace.so")
 SOURCES = ["mace_host.cpp", "mace_solve.cpp", "mace_server.cpp", "mace_autotune.cpp", "mace_kernels.hip", "mace_sweep_s4f32.hip", "mace_sweep_s4f16.hip",
-           "mace_sweep_s8f32.hip", "mace_sweep_s8f16.hip"]
+           "mace_sweep_s8f32.hip", "mace_sweep_s8f16.hip", "mace_sweep_gen.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

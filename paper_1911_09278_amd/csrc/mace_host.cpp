@@ -72,9 +72,6 @@ static int build_partition(mace_system* s, const int32_t* view_to_agent) {
     if (s->views[a].empty()) return fail(MACE_E_PARTITION, "agent %d owns no view", a);
     s->Kmax = std::max<int>(s->Kmax, (int)s->views[a].size());
   }
-  if (s->Kmax > kRowLanes * kMaxSlots)
-    return fail(MACE_E_PARTITION, "an agent owns %d views; at most %d are supported", s->Kmax,
-                kRowLanes * kMaxSlots);
   s->slots = (s->Kmax + kRowLanes - 1) / kRowLanes;
   s->kpad = s->slots * kRowLanes;
   s->estride = (int64_t)s->Kmax * s->n_ch;
@@ -136,11 +133,34 @@ struct HostPack {
   std::vector<BandEnt> band;
   std::vector<int> brows;
   std::vector<int> row_src;
+  std::vector<float> gval;     // general records
+  std::vector<uint16_t> grow;
 };
 
-static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const float* val,
-                  HostPack& hp) {
-  const int N = s->N, n = s->n, kpad = s->kpad, S = s->S;
+// Agent-block row map and the super-voxel colour lists (both formats).
+static void finish_layout(mace_system* s, HostPack& hp) {
+  const int N = s->N;
+  // agent-block row -> global sinogram row
+  hp.row_src.assign((size_t)N * s->estride, -1);
+  for (int a = 0; a < N; ++a)
+    for (size_t kl = 0; kl < s->views[a].size(); ++kl)
+      for (int d = 0; d < s->n_ch; ++d)
+        hp.row_src[(size_t)a * s->estride + kl * s->n_ch + d] = s->views[a][kl] * s->n_ch + d;
+  // colour lists: SVs of colour c = (sx mod 2) + 2 (sy mod 2), in a seeded
+  // random order so that the SVs processed together are spread over the image
+  for (int c = 0; c < 4; ++c) s->colour_svs[c].clear();
+  for (int sv = 0; sv < s->n_sv; ++sv) {
+    int sy = sv / s->gx, sx = sv % s->gx;
+    s->colour_svs[(sx & 1) + 2 * (sy & 1)].push_back(sv);
+  }
+  for (int c = 0; c < 4; ++c) {
+    std::mt19937_64 rng(0x9e3779b97f4a7c15ULL + c);
+    std::shuffle(s->colour_svs[c].begin(), s->colour_svs[c].end(), rng);
+  }
+}
+
+static void sv_tiling(mace_system* s) {
+  const int S = s->S;
   s->gx = (s->nx + S - 1) / S;
   s->gy = (s->ny + S - 1) / S;
   s->n_sv = s->gx * s->gy;
@@ -150,6 +170,151 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
     int sh = std::min(S, s->ny - sy * S), sw = std::min(S, s->nx - sx * S);
     s->sv_pix0[sv + 1] = s->sv_pix0[sv] + sh * sw;
   }
+}
+
+// General records (any sparsity pattern): for each (agent, super-voxel, view
+// of the agent) the band is the channel range the SV's pixels touch in that
+// view; a pixel's record lists its nonzeros in the agent's rows as (LDS row
+// of the band, value), padded to nzp entries with zero values on the task's
+// first dummy row B.
+static int repack_general(mace_system* s, const int64_t* cp, const int32_t* row, const float* val,
+                          HostPack& hp) {
+  const int N = s->N, n = s->n, kpad = s->kpad, S = s->S;
+  sv_tiling(s);
+  // entries per (agent, column); nzp = the largest, rounded up to 16
+  int maxc = 0;
+  {
+    std::vector<int> cnt(N);
+    for (int64_t c = 0; c < n; ++c) {
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int64_t q = cp[c]; q < cp[c + 1]; ++q) ++cnt[s->view_agent[row[q] / s->n_ch]];
+      for (int a = 0; a < N; ++a) maxc = std::max(maxc, cnt[a]);
+    }
+  }
+  s->nzp = std::max(kRowLanes, (maxc + kRowLanes - 1) / kRowLanes * kRowLanes);
+  const size_t nrec = (size_t)N * n;
+  hp.gval.assign(nrec * s->nzp, 0.0f);
+  hp.grow.assign(nrec * s->nzp, 0);
+  hp.band.assign((size_t)N * s->n_sv * kpad, BandEnt{0, 0, 0});
+  hp.brows.assign((size_t)N * s->n_sv, 0);
+  std::vector<int> local(s->n_views);
+  for (int a = 0; a < N; ++a)
+    for (size_t k = 0; k < s->views[a].size(); ++k) local[s->views[a][k]] = (int)k;
+  std::atomic<int> err{0};
+  std::atomic<int> bmax{0};
+  const int nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t)
+    th.emplace_back([&, t] {
+      std::vector<int> lo(s->n_views), hi(s->n_views), ldsr(s->n_views);
+      for (int sv = t; sv < s->n_sv && !err; sv += nth) {
+        const int sy = sv / s->gx, sx = sv % s->gx;
+        const int y0 = sy * S, x0 = sx * S;
+        const int sh = std::min(S, s->ny - y0), sw = std::min(S, s->nx - x0);
+        const int npix = sh * sw;
+        std::fill(lo.begin(), lo.end(), 1 << 30);
+        std::fill(hi.begin(), hi.end(), -1);
+        for (int j = 0; j < npix; ++j) {
+          const int64_t col = (int64_t)(y0 + j / sw) * s->nx + x0 + j % sw;
+          for (int64_t q = cp[col]; q < cp[col + 1]; ++q) {
+            const int k = row[q] / s->n_ch, d = row[q] % s->n_ch;
+            lo[k] = std::min(lo[k], d);
+            hi[k] = std::max(hi[k], d);
+          }
+        }
+        std::vector<int> B(N, 0);
+        for (int a = 0; a < N; ++a) {
+          const size_t asv = (size_t)a * s->n_sv + sv;
+          for (size_t kl = 0; kl < s->views[a].size(); ++kl) {
+            const int k = s->views[a][kl];
+            if (hi[k] < 0) continue;
+            BandEnt b;
+            b.gstart = (uint32_t)((int64_t)kl * s->n_ch + lo[k]);
+            b.width = (uint16_t)(hi[k] - lo[k] + 1);
+            b.lds_row = (uint16_t)B[a];
+            ldsr[k] = B[a];
+            B[a] += b.width;
+            if (B[a] + 2 > 65535) {
+              err = 3;
+              return;
+            }
+            hp.band[asv * kpad + kl] = b;
+          }
+          // views that miss the SV, and padding views: width 0 on the dummy rows
+          for (int kl = 0; kl < kpad; ++kl)
+            if (hp.band[asv * kpad + kl].width == 0) hp.band[asv * kpad + kl] = BandEnt{0, (uint16_t)B[a], 0};
+          hp.brows[asv] = B[a];
+          int cur = bmax.load();
+          while (B[a] + 2 > cur && !bmax.compare_exchange_weak(cur, B[a] + 2)) {
+          }
+        }
+        std::vector<int> fillc(N);
+        for (int j = 0; j < npix; ++j) {
+          const int64_t col = (int64_t)(y0 + j / sw) * s->nx + x0 + j % sw;
+          std::fill(fillc.begin(), fillc.end(), 0);
+          for (int a = 0; a < N; ++a) {
+            const size_t rec = (size_t)a * n + s->sv_pix0[sv] + j;
+            for (int q = 0; q < s->nzp; ++q) hp.grow[rec * s->nzp + q] = (uint16_t)B[a];
+          }
+          for (int64_t q = cp[col]; q < cp[col + 1]; ++q) {
+            const int k = row[q] / s->n_ch, d = row[q] % s->n_ch;
+            const int a = s->view_agent[k];
+            const size_t rec = (size_t)a * n + s->sv_pix0[sv] + j;
+            const size_t e = rec * s->nzp + fillc[a]++;
+            hp.gval[e] = val[q];
+            hp.grow[e] = (uint16_t)(ldsr[k] + d - lo[k]);
+          }
+        }
+      }
+    });
+  for (auto& x : th) x.join();
+  if (err == 3) return fail(MACE_E_MATRIX, "super-voxel band exceeds 65533 rows; use a smaller sv_size");
+  s->bmax = (bmax.load() + 1) & ~1;
+  if (s->bmax < 2) s->bmax = 2;
+  finish_layout(s, hp);
+  return MACE_OK;
+}
+
+// Every index the general kernel forms stays inside its buffer.
+static int check_pack_general(const mace_system* s, const HostPack& hp) {
+  const int N = s->N, kpad = s->kpad;
+  for (int a = 0; a < N; ++a) {
+    const int64_t K = (int64_t)s->views[a].size();
+    for (int sv = 0; sv < s->n_sv; ++sv) {
+      const size_t asv = (size_t)a * s->n_sv + sv;
+      const int B = hp.brows[asv];
+      if (B < 0 || B + 2 > s->bmax) return fail(MACE_E_MATRIX, "check: band rows %d exceed bmax %d", B, s->bmax);
+      int rows = 0;
+      for (int kl = 0; kl < kpad; ++kl) {
+        const BandEnt& b = hp.band[asv * kpad + kl];
+        if (b.width == 0) continue;
+        if (kl >= K) return fail(MACE_E_MATRIX, "check: band entry on a padding view");
+        if ((int)b.lds_row + b.width > B) return fail(MACE_E_MATRIX, "check: band overruns its rows");
+        if ((int64_t)b.gstart / s->n_ch != kl || ((int64_t)b.gstart + b.width - 1) / s->n_ch != kl)
+          return fail(MACE_E_MATRIX, "check: band crosses a view boundary");
+        rows += b.width;
+      }
+      if (rows != B) return fail(MACE_E_MATRIX, "check: band rows do not add up");
+      const int npix = s->sv_pix0[sv + 1] - s->sv_pix0[sv];
+      if (npix < 1 || npix > s->S * s->S) return fail(MACE_E_MATRIX, "check: bad SV pixel count");
+      for (int j = 0; j < npix; ++j) {
+        const size_t rec = (size_t)a * s->n + s->sv_pix0[sv] + j;
+        for (int q = 0; q < s->nzp; ++q) {
+          const int r = hp.grow[rec * s->nzp + q];
+          if (r > B || (r == B && hp.gval[rec * s->nzp + q] != 0.0f))
+            return fail(MACE_E_MATRIX, "check: record row %d outside its band (%d rows)", r, B);
+        }
+      }
+    }
+  }
+  if (s->sv_pix0[s->n_sv] != s->n) return fail(MACE_E_MATRIX, "check: SVs do not tile the image");
+  return MACE_OK;
+}
+
+static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const float* val,
+                  HostPack& hp) {
+  const int N = s->N, n = s->n, kpad = s->kpad, S = s->S;
+  sv_tiling(s);
   // agent-local view index of every view
   std::vector<int> local(s->n_views);
   for (int a = 0; a < N; ++a)
@@ -307,29 +472,16 @@ static int repack(mace_system* s, const int64_t* cp, const int32_t* row, const f
   s->wmax = wmaxa.load();
   if (s->bmax < 2) s->bmax = 2;
 
-  // agent-block row -> global sinogram row
-  hp.row_src.assign((size_t)N * s->estride, -1);
-  for (int a = 0; a < N; ++a)
-    for (size_t kl = 0; kl < s->views[a].size(); ++kl)
-      for (int d = 0; d < s->n_ch; ++d)
-        hp.row_src[(size_t)a * s->estride + kl * s->n_ch + d] = s->views[a][kl] * s->n_ch + d;
-
-  // colour lists: SVs of colour c = (sx mod 2) + 2 (sy mod 2), in a seeded
-  // random order so that the SVs processed together are spread over the image
-  for (int c = 0; c < 4; ++c) s->colour_svs[c].clear();
-  for (int sv = 0; sv < s->n_sv; ++sv) {
-    int sy = sv / s->gx, sx = sv % s->gx;
-    s->colour_svs[(sx & 1) + 2 * (sy & 1)].push_back(sv);
-  }
-  for (int c = 0; c < 4; ++c) {
-    std::mt19937_64 rng(0x9e3779b97f4a7c15ULL + c);
-    std::shuffle(s->colour_svs[c].begin(), s->colour_svs[c].end(), rng);
-  }
+  finish_layout(s, hp);
   return MACE_OK;
 }
 
 static int upload_pack(mace_system* s, const HostPack& hp) {
-  HIP_OK(s->adel.upload(hp.adel.data(), hp.adel.size()));
+  if (!hp.adel.empty()) HIP_OK(s->adel.upload(hp.adel.data(), hp.adel.size()));
+  if (!hp.gval.empty()) {
+    HIP_OK(s->gval.upload(hp.gval.data(), hp.gval.size()));
+    HIP_OK(s->grow.upload(hp.grow.data(), hp.grow.size()));
+  }
   if (!hp.aval.empty()) HIP_OK(s->aval.upload(hp.aval.data(), hp.aval.size()));
   if (!hp.hval.empty()) {
     HIP_OK(s->hval.upload(hp.hval.data(), hp.hval.size()));
@@ -340,7 +492,8 @@ static int upload_pack(mace_system* s, const HostPack& hp) {
   HIP_OK(s->d_sv_pix0.upload(s->sv_pix0.data(), s->sv_pix0.size()));
   HIP_OK(s->row_src.upload(hp.row_src.data(), hp.row_src.size()));
   s->matrix_bytes = (int64_t)(s->aval.bytes() + s->hval.bytes() + s->hscale.bytes() +
-                              s->adel.bytes() + s->band.bytes() + s->band_rows.bytes());
+                              s->adel.bytes() + s->band.bytes() + s->band_rows.bytes() +
+                              s->gval.bytes() + s->grow.bytes());
   return MACE_OK;
 }
 
@@ -401,7 +554,7 @@ static int check_pack(const mace_system* s, const HostPack& hp) {
 // 79 KB each for the 45-view workloads), fewer when a row's band, halo and
 // scratch would not fit 16 to the 160 KiB of LDS (many views per agent).
 static int pick_rows_per_block(mace_system* s) {
-  s->rpb = sv_rows_per_block(s->bmax, s->S, s->kpad);
+  s->rpb = sv_rows_per_block(s->bmax, s->S, s->kpad, s->format);
   if (s->rpb == 0)
     return fail(MACE_E_ARG,
                 "a super-voxel band of %d rows needs more than 40 KiB of LDS per row; %s", s->bmax,
@@ -562,6 +715,10 @@ void mace::fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, doub
   a.hscale = s->hscale.p;
   a.fp16 = fp16 ? 1 : 0;
   a.adel = s->adel.p;
+  a.format = s->format;
+  a.gval = s->gval.p;
+  a.grow = s->grow.p;
+  a.nzp = s->nzp;
   a.band = s->band.p;
   a.band_rows = s->band_rows.p;
   a.estride = s->estride;
@@ -596,6 +753,42 @@ int mace::check_prior(const mace_prior* pr) {
   return MACE_OK;
 }
 
+// ---------------------------------------------------------------- layout choice
+// Builds the device tables in hp for the record format the options ask for
+// (0: compact when the matrix and options allow it, else general; 1:
+// compact; 2: general), checks every index the kernels form, and picks the
+// rows per workgroup.  The compact records need super-voxel sides 4 or 8, at
+// most 128 views per agent, at most two nonzeros per (column, view) on
+// adjacent channels and bands of at most 16 (S = 8) or 8 (S = 4) channels;
+// the general records take any matrix, FP32 values only.
+static int build_layout(mace_system* s, const int64_t* cp, const int32_t* row, const float* val,
+                        int fmt_req, HostPack& hp) {
+  const bool small_s = s->S == 4 || s->S == 8;
+  const bool compact_ok = small_s && s->Kmax <= kRowLanes * kMaxSlots;
+  if (fmt_req == 1 && !compact_ok)
+    return fail(MACE_E_ARG, "the compact record format needs sv_size 4 or 8 and at most %d views "
+                            "per agent", kRowLanes * kMaxSlots);
+  int rc;
+  if (fmt_req != 2 && compact_ok) {
+    s->format = 0;
+    rc = repack(s, cp, row, val, hp);
+    if (rc == MACE_OK) rc = check_pack(s, hp);
+    if (rc == MACE_OK) rc = pick_rows_per_block(s);
+    if (rc != MACE_E_MATRIX || fmt_req == 1 || s->precision == 1) return rc;
+    hp = HostPack{};  // not representable in the compact records
+  }
+  if (s->precision == 1)
+    return fail(MACE_E_ARG, "FP16 matrix values need the compact record format (sv_size 4 or 8, "
+                            "at most %d views per agent, at most two adjacent nonzeros per view)",
+                kRowLanes * kMaxSlots);
+  s->format = 1;
+  s->kpad = (s->Kmax + kRowLanes - 1) / kRowLanes * kRowLanes;
+  rc = repack_general(s, cp, row, val, hp);
+  if (rc == MACE_OK) rc = check_pack_general(s, hp);
+  if (rc == MACE_OK) rc = pick_rows_per_block(s);
+  return rc;
+}
+
 // ---------------------------------------------------------------- ABI
 extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
                                 const int32_t* row_idx, const float* val, int32_t n_agents,
@@ -626,8 +819,10 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
   s->N = n_agents;
   if (opts) {
     if (opts->precision != 0 && opts->precision != 1) return fail(MACE_E_ARG, "precision must be 0 or 1");
-    if (opts->sv_size != 0 && opts->sv_size != 4 && opts->sv_size != 8)
-      return fail(MACE_E_ARG, "sv_size must be -1 (autotune), 0 (automatic), 4 or 8");
+    if (opts->sv_size != 0 && opts->sv_size != 4 && opts->sv_size != 8 && opts->sv_size != 16 &&
+        opts->sv_size != 32)
+      return fail(MACE_E_ARG, "sv_size must be -1 (autotune), 0 (automatic), 4, 8, 16 or 32");
+    if (opts->format < 0 || opts->format > 2) return fail(MACE_E_ARG, "format must be 0, 1 or 2");
     if (opts->rows_per_agent < 0) return fail(MACE_E_ARG, "rows_per_agent must be >= 0");
     if (opts->fp32_tail_iters < 0) return fail(MACE_E_ARG, "fp32_tail_iters must be >= 0");
     s->precision = opts->precision;
@@ -644,11 +839,7 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
   if (rc) return rc;
   {
     HostPack hp;
-    rc = repack(s.get(), col_ptr, row_idx, val, hp);
-    if (rc) return rc;
-    rc = check_pack(s.get(), hp);
-    if (rc) return rc;
-    rc = pick_rows_per_block(s.get());
+    rc = build_layout(s.get(), col_ptr, row_idx, val, opts ? opts->format : 0, hp);
     if (rc) return rc;
     rc = upload_pack(s.get(), hp);
     if (rc) return rc;
@@ -680,8 +871,11 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
   s.n_ch = geom->n_channels;
   s.N = n_agents;
   if (opts) {
-    if (opts->sv_size != 0 && opts->sv_size != 4 && opts->sv_size != 8)
-      return fail(MACE_E_ARG, "sv_size must be 0 (default 4), 4 or 8");
+    if (opts->sv_size != 0 && opts->sv_size != 4 && opts->sv_size != 8 && opts->sv_size != 16 &&
+        opts->sv_size != 32)
+      return fail(MACE_E_ARG,
+                  "sv_size must be 0 (automatic: 8 from 256 x 256 pixels on, else 4), 4, 8, 16 or 32");
+    if (opts->format < 0 || opts->format > 2) return fail(MACE_E_ARG, "format must be 0, 1 or 2");
     s.precision = opts->precision;
     s.S = opts->sv_size;
     s.rows_per_agent = opts->rows_per_agent;
@@ -693,11 +887,7 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
   rc = check_matrix(&s, col_ptr, row_idx, val);
   if (rc) return rc;
   HostPack hp;
-  rc = repack(&s, col_ptr, row_idx, val, hp);
-  if (rc) return rc;
-  rc = check_pack(&s, hp);
-  if (rc) return rc;
-  rc = pick_rows_per_block(&s);
+  rc = build_layout(&s, col_ptr, row_idx, val, opts ? opts->format : 0, hp);
   if (rc) return rc;
   const int P = default_rows_per_agent(&s);
   for (int only = -1; only < s.N; ++only) {
@@ -711,7 +901,7 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
     }
     if (only >= 2) break;
   }
-  if (lds_bytes) *lds_bytes = (int64_t)sv_lds_bytes(s.bmax, s.S, s.kpad);
+  if (lds_bytes) *lds_bytes = (int64_t)sv_lds_bytes(s.bmax, s.S, s.kpad, s.format);
   return MACE_OK;
 }
 
@@ -727,6 +917,7 @@ extern "C" int mace_get_config(const mace_system* s, mace_opts* out) {
   out->rows_per_agent = default_rows_per_agent(s);
   out->fp32_tail_iters = s->fp32_tail;
   out->refresh_every = s->refresh_every;
+  out->format = s->format == 1 ? 2 : 1;
   return MACE_OK;
 }
 
@@ -734,6 +925,16 @@ extern "C" int mace_set_relaxation(mace_system* s, double relax) {
   if (!s) return fail(MACE_E_ARG, "NULL system");
   if (!(relax > 0.0 && relax <= 1.0)) return fail(MACE_E_ARG, "relaxation must be in (0, 1]");
   s->relax = relax;
+  return MACE_OK;
+}
+
+extern "C" int mace_set_fp32_tail(mace_system* s, int32_t iters) {
+  if (!s) return fail(MACE_E_ARG, "NULL system");
+  if (iters < 0) return fail(MACE_E_ARG, "iters must be >= 0");
+  if (s->precision != 1) return fail(MACE_E_ARG, "the system's matrix values are FP32 already");
+  if (iters > 0 && !s->aval.p)
+    return fail(MACE_E_ARG, "the system holds no FP32 values: load it with fp32_tail_iters > 0");
+  s->fp32_tail = iters;
   return MACE_OK;
 }
 

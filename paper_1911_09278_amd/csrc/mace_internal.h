@@ -80,9 +80,15 @@ struct SvArgs {
   int rpb;              // rows per workgroup (16, 8 or 4); the block has rpb * 16 threads
   int kstr;             // record values per (agent, pixel): the largest view count of an agent
   int hpass;            // MACE-PnP: passes of the denoiser H after each epilogue (0: plain MACE)
+  int format;           // 0: compact records (sv_kernel); 1: general records (sv_kernel_gen)
+  const float* gval;    // general records: values [N * n][nzp]
+  const uint16_t* grow; // general records: LDS rows of the task's band [N * n][nzp]
+  int nzp;              // general records: entries per (agent, pixel), a multiple of 16
 };
 
-// Per-variant sweep launchers (mace_sweep_*.hip).
+// Per-variant sweep launchers (mace_sweep_*.hip); general records for
+// super-voxel sides 4, 8, 16, 32 (mace_sweep_gen.hip).
+hipError_t launch_sv_gen(const SvArgs& a, int mode, int grid, size_t lds, hipStream_t st);
 hipError_t launch_sv_s4f32(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
 hipError_t launch_sv_s4f16(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
 hipError_t launch_sv_s8f32(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
@@ -90,10 +96,11 @@ hipError_t launch_sv_s8f16(const SvArgs& a, int mode, int slots, int grid, size_
 
 // Launchers (defined in mace_kernels.hip).
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
-// Rows per workgroup: the most of 16, 8, 4 whose LDS fits in 160 KiB (0 if
-// none does), and the LDS bytes of such a workgroup.
-int sv_rows_per_block(int bmax, int S, int kpad);
-size_t sv_lds_bytes(int bmax, int S, int kpad);
+// Rows per workgroup: the most of 16, 8, 4 (general records: down to 1)
+// whose LDS fits in 160 KiB (0 if none does), and the LDS bytes of such a
+// workgroup.
+int sv_rows_per_block(int bmax, int S, int kpad, int format);
+size_t sv_lds_bytes(int bmax, int S, int kpad, int format);
 // Doubles the epilogue needs after a slot's task partials.
 size_t epilogue_scratch_doubles();
 hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int nparts,

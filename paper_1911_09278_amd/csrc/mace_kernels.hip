@@ -5,22 +5,29 @@
 
 #include "mace_internal.h"
 #include "mace_sweep.h"
+#include "mace_sweep_gen.h"
 
 namespace mace {
 
-int sv_rows_per_block(int bmax, int S, int kpad) {
-  for (int rpb = kMaxRowsPerBlock; rpb >= 4; rpb /= 2)
-    if ((size_t)rpb * row_lds_bytes(bmax, S, kpad) <= kMaxLdsBytes) return rpb;
+static size_t row_bytes(int bmax, int S, int kpad, int format) {
+  return format == 1 ? gen_row_lds_bytes(bmax, S) : row_lds_bytes(bmax, S, kpad);
+}
+
+int sv_rows_per_block(int bmax, int S, int kpad, int format) {
+  const int lo = format == 1 ? 1 : 4;
+  for (int rpb = kMaxRowsPerBlock; rpb >= lo; rpb /= 2)
+    if ((size_t)rpb * row_bytes(bmax, S, kpad, format) <= kMaxLdsBytes) return rpb;
   return 0;
 }
 
-size_t sv_lds_bytes(int bmax, int S, int kpad) {
-  const int rpb = sv_rows_per_block(bmax, S, kpad);
-  return (size_t)(rpb > 0 ? rpb : 4) * row_lds_bytes(bmax, S, kpad);
+size_t sv_lds_bytes(int bmax, int S, int kpad, int format) {
+  const int rpb = sv_rows_per_block(bmax, S, kpad, format);
+  return (size_t)(rpb > 0 ? rpb : 1) * row_bytes(bmax, S, kpad, format);
 }
 
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st) {
   if (grid <= 0) return hipSuccess;
+  if (a.format == 1) return launch_sv_gen(a, mode, grid, lds, st);
   if (a.S == 4) return a.fp16 ? launch_sv_s4f16(a, mode, slots, grid, lds, st)
                               : launch_sv_s4f32(a, mode, slots, grid, lds, st);
   if (a.S == 8) return a.fp16 ? launch_sv_s8f16(a, mode, slots, grid, lds, st)

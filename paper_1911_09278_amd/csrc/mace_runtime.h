@@ -136,6 +136,8 @@ struct mace_system {
   int rows_per_agent = 0;
   int fp32_tail = 0;
   int refresh_every = 0;
+  int format = 0;  // 0: compact records (sv_kernel), 1: general records (sv_kernel_gen)
+  int nzp = 0;     // general records: entries per (agent, pixel)
   int64_t estride = 0;
   std::vector<int> view_agent;          // [n_views]
   std::vector<std::vector<int>> views;  // agent -> its views, ascending
@@ -146,6 +148,8 @@ struct mace_system {
   mace::DevBuf<__half2> hval;
   mace::DevBuf<float> hscale;
   mace::DevBuf<uint32_t> adel;
+  mace::DevBuf<float> gval;     // general records
+  mace::DevBuf<uint16_t> grow;
   mace::DevBuf<mace::BandEnt> band;
   mace::DevBuf<int> band_rows;
   mace::DevBuf<int> d_sv_pix0;

@@ -1,0 +1,233 @@
+#pragma once
+// Super-voxel ICD sweep for matrices of any sparsity pattern (general
+// records).  Same algorithm and task structure as sv_kernel (mace_sweep.h):
+// one 16-lane row per (agent, super-voxel) task, the task's error-sinogram
+// band staged in LDS, per pixel theta1 / theta2 / the prior's majoriser /
+// the prox term summed over the row, the coordinate step, the band update,
+// the band's change added to the agent's error sinogram with atomics, and
+// the reflection + Mann update with FP64 residual partials.  What differs:
+//   * a record is the list of the pixel's nonzeros in the agent's rows, as
+//     (LDS row of the band, value) pairs padded to nzp entries (a multiple
+//     of 16) with zero values on the task's dummy row; a column may have any
+//     number of nonzeros per view, on any channels;
+//   * a view's band may be wider than 16 channels, and an agent may own any
+//     number of views: the band is staged and written back view by view in
+//     chunks of 16 channels;
+//   * the staged copy of e that the write-back subtracts lives in LDS;
+//   * super-voxel sides 4, 8, 16 and 32.
+// Loops over records, views and pixels are not unrolled.  FP32 values only.
+#include <hip/hip_runtime.h>
+
+#include "mace_internal.h"
+#include "mace_sweep.h"
+
+namespace mace {
+
+// LDS bytes of one row of the general kernel: band (e, Lambda), the staged
+// e, the halo tile and v / theta2 of the super-voxel's pixels.
+__host__ __device__ inline size_t gen_row_lds_bytes(int bmax, int S) {
+  size_t per_row = (size_t)bmax * 12 + (size_t)halo_cells(S) * 4 + (size_t)S * S * 8;
+  per_row = (per_row + 7) & ~(size_t)7;
+  const size_t red = kRowLanes * 3 * sizeof(double);
+  return per_row > red ? per_row : red;
+}
+
+template <int MODE, int S>
+__global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
+  constexpr int HS = S + 2;
+  constexpr int NHC = halo_cells(S);
+  extern __shared__ __align__(16) char smem[];
+  const int lane64 = threadIdx.x & 63;
+  const int lr = lane64 & 15;
+  const int rib = threadIdx.x >> 4;  // row in block
+  const int row = blockIdx.x * a.rpb + rib;
+  const size_t per_row = gen_row_lds_bytes(a.bmax, S);
+  char* base = smem + rib * per_row;
+  float2* band = reinterpret_cast<float2*>(base);
+  float* e0l = reinterpret_cast<float*>(base + (size_t)a.bmax * 8);
+  float* halo = e0l + a.bmax;
+  float* vv = halo + NHC;
+  float* t2 = vv + S * S;
+
+  const int ndi = (lr < 3) ? -1 : (lr < 5 ? 0 : 1);
+  const int ndj = (lr == 0 || lr == 3 || lr == 5) ? -1 : ((lr == 1 || lr == 6) ? 0 : 1);
+  const float nbw = lr < 8 ? ((ndi != 0 && ndj != 0) ? a.bdiag : a.bedge) * a.invN : 0.0f;
+  const int noff = lr < 8 ? ndi * HS + ndj : 0;
+  const int ndi8 = lr < 8 ? ndi : 0, ndj8 = lr < 8 ? ndj : 0;
+  const float proxw = lr == 8 ? a.is2 : 0.0f;
+  const bool row_ok = row < a.R;
+  const int* my_tasks = a.tasks + (size_t)(row_ok ? row : 0) * a.T;
+
+  for (int t = 0; t < a.T; ++t) {
+    const int raw = row_ok ? my_tasks[t] : -1;
+    if (raw < 0) continue;
+    const int task = raw & ((1 << kSlotShift) - 1);
+    const SlotDesc* sd = a.slots + (raw >> kSlotShift);
+    if (!sd->active || sd->prec != 0) continue;
+    const int agent = task / a.n_sv;
+    const int sv = task - agent * a.n_sv;
+    const size_t asv = (size_t)agent * a.n_sv + sv;
+    const int sy = sv / a.gx, sx = sv - sy * a.gx;
+    const int y0 = sy * S, x0 = sx * S;
+    const int sh = min(S, a.ny - y0), sw = min(S, a.nx - x0);
+    const int npix = sh * sw;
+    const size_t img = (size_t)agent * a.n;
+    gptr<float> eag = glb(sd->e) + (size_t)agent * a.estride;
+    gptr<const float> lam = glb(sd->lam) + (size_t)agent * a.estride;
+    gptr<float> cX = glb(sd->X);
+    gptr<float> cw = glb(sd->w);
+    gptr<const float> cwbar = glb(sd->wbar);
+    gptr<float> cth2 = glb(sd->th2);
+    gptr<double> cpart = glb(sd->part);
+    const BandEnt* be = a.band + asv * a.kpad;
+    const int B = a.band_rows[asv];
+
+    // ---- 1. stage the band view by view, 16 channels at a time ----
+    for (int k = 0; k < a.kpad; ++k) {
+      const BandEnt b = be[k];
+      for (int c = lr; c < b.width; c += kRowLanes) {
+        const uint32_t gi = b.gstart + (uint32_t)c;
+        const float ev = MODE == kSweep ? load_e(eag + gi) : 0.0f;
+        const float lv = MODE != kRefresh ? lam[gi] : 0.0f;
+        band[b.lds_row + c] = make_float2(ev, lv);
+        if (MODE == kSweep) e0l[b.lds_row + c] = ev;
+      }
+    }
+    if (lr < 2) band[B + lr] = make_float2(0.0f, 0.0f);
+    if (MODE != kTheta2) {
+      for (int c = lr; c < HS * HS; c += kRowLanes) {
+        const int hi = c / HS, hj = c - hi * HS;
+        const int iy = y0 - 1 + hi, ix = x0 - 1 + hj;
+        const bool in = iy >= 0 && iy < a.ny && ix >= 0 && ix < a.nx;
+        halo[c] = in ? cX[img + (size_t)iy * a.nx + ix] : 0.0f;
+      }
+    }
+    if (MODE == kSweep) {
+      for (int p = lr; p < npix; p += kRowLanes) {
+        const int pi = p / sw, pj = p - (p / sw) * sw;
+        const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
+        vv[p] = 2.0f * cwbar[pix] - cw[img + pix];
+        t2[p] = cth2[img + pix];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // ---- 2. pixel loop ----
+    const size_t rec0 = (size_t)agent * a.n + (size_t)a.sv_pix0[sv];
+    for (int j = 0; j < npix; ++j) {
+      const int pi = j / sw, pj = j - (j / sw) * sw;
+      const int cidx = (pi + 1) * HS + pj + 1;
+      const float* gv = a.gval + (rec0 + j) * (size_t)a.nzp;
+      const uint16_t* gr = a.grow + (rec0 + j) * (size_t)a.nzp;
+      if (MODE == kSweep) {
+        float part = 0.0f;
+        for (int q = lr; q < a.nzp; q += kRowLanes) {
+          const float2 p = band[gr[q]];
+          part += gv[q] * p.y * p.x;
+        }
+        const float zs = halo[cidx];
+        const float nbv = halo[cidx + noff];
+        const float vj = vv[j], tj = t2[j];
+        const int iy = y0 + pi + ndi8, ix = x0 + pj + ndj8;
+        const float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+        const float d = zs - nbv;
+        const float wgt = nbw * nin * prior_curv(a, d);
+        const float gl = wgt * d + proxw * (zs - vj) - part;
+        const float G = row_sum16(gl);
+        const float H = row_sum16(wgt);
+        const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(tj + H + a.is2);
+        // the rows of one column are distinct; padding entries add 0 to
+        // the dummy row
+        for (int q = lr; q < a.nzp; q += kRowLanes) band[gr[q]].x -= gv[q] * alpha;
+        if (lr == 0) halo[cidx] = zs + alpha;
+      } else if (MODE == kTheta2) {
+        float part = 0.0f;
+        for (int q = lr; q < a.nzp; q += kRowLanes) {
+          const float av = gv[q];
+          part += av * av * band[gr[q]].y;
+        }
+        const float th = row_sum16(part);
+        if (lr == 0) cth2[img + (size_t)(y0 + pi) * a.nx + x0 + pj] = th;
+      } else {
+        const float xs = halo[cidx];
+        for (int q = lr; q < a.nzp; q += kRowLanes) band[gr[q]].x -= gv[q] * xs;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+
+    // ---- 3. write back, view by view ----
+    if (MODE != kTheta2) {
+      for (int k = 0; k < a.kpad; ++k) {
+        const BandEnt b = be[k];
+        for (int c = lr; c < b.width; c += kRowLanes) {
+          float d = band[b.lds_row + c].x;
+          if (MODE == kSweep) d -= e0l[b.lds_row + c];
+          add_e(eag + b.gstart + c, d);
+        }
+      }
+    }
+    if (MODE == kSweep) {
+      double pn = 0.0, pd = 0.0, px = 0.0;
+      for (int p = lr; p < npix; p += kRowLanes) {
+        const int pi = p / sw, pj = p - (p / sw) * sw;
+        const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
+        const float xn = halo[(pi + 1) * HS + pj + 1];
+        cX[img + pix] = xn;
+        if (a.mann) {
+          const float wo = cw[img + pix], wb = cwbar[pix];
+          const float v = 2.0f * wb - wo;
+          cw[img + pix] = a.rho * (2.0f * xn - v) + (1.0f - a.rho) * wo;
+          const double dd = (double)xn - (double)wb;
+          pn += dd * dd;
+          pd += (double)wo * (double)wo;
+          px += (double)xn * (double)xn;
+        }
+      }
+      if (a.mann) {
+        double* red = reinterpret_cast<double*>(base);
+        __builtin_amdgcn_wave_barrier();
+        red[lr * 3 + 0] = pn;
+        red[lr * 3 + 1] = pd;
+        red[lr * 3 + 2] = px;
+        __builtin_amdgcn_wave_barrier();
+        if (lr == 0) {
+          double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+          for (int l = 0; l < kRowLanes; ++l) {
+            s0 += red[l * 3 + 0];
+            s1 += red[l * 3 + 1];
+            s2 += red[l * 3 + 2];
+          }
+          cpart[(size_t)task * 4 + 0] = s0;
+          cpart[(size_t)task * 4 + 1] = s1;
+          cpart[(size_t)task * 4 + 2] = s2;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    if (a.strict) __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+template <int MODE, int SV>
+inline hipError_t launch_gen_mode(const SvArgs& a, int grid, size_t lds, hipStream_t st) {
+  static std::atomic<bool> attr_set{false};
+  if (!attr_set.load(std::memory_order_acquire)) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel_gen<MODE, SV>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kMaxLdsBytes);
+    if (e != hipSuccess) return e;
+    attr_set.store(true, std::memory_order_release);
+  }
+  hipLaunchKernelGGL((sv_kernel_gen<MODE, SV>), dim3(grid), dim3(a.rpb * kRowLanes), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int SV>
+inline hipError_t launch_gen_s(const SvArgs& a, int mode, int grid, size_t lds, hipStream_t st) {
+  if (mode == kSweep) return launch_gen_mode<kSweep, SV>(a, grid, lds, st);
+  if (mode == kTheta2) return launch_gen_mode<kTheta2, SV>(a, grid, lds, st);
+  return launch_gen_mode<kRefresh, SV>(a, grid, lds, st);
+}
+
+}  // namespace mace

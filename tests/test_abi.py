@@ -82,22 +82,63 @@ def test_rejects_bad_partition_and_args():
     with pytest.raises(m.MaceError) as e:
         m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 4, precision=3)
     assert e.value.code == m.MACE_E_ARG
-    # one agent with more than 128 views
+    with pytest.raises(m.MaceError) as e:
+        m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, format=3)
+    assert e.value.code == m.MACE_E_ARG
+    with pytest.raises(m.MaceError) as e:
+        m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, sv_size=12)
+    assert e.value.code == m.MACE_E_ARG
+
+
+def test_record_format_choice():
+    """The compact records cover 1 mm channels with at most 128 views per
+    agent and 4 / 8 pixel super-voxels; anything else takes the general
+    records (check_layout builds and checks either without a device)."""
+    import paper_1911_09278_amd as m
+    # one agent with more than 128 views: general records only
     g2 = mi.Geometry(8, 8, 130, 12)
     cp3, row3, val3 = mi.system_matrix(g2)
+    assert m.check_layout(g2.nx, g2.ny, g2.n_views, g2.n_channels, cp3, row3, val3, 1) > 0
     with pytest.raises(m.MaceError) as e:
-        m.System(g2.nx, g2.ny, g2.n_views, g2.n_channels, cp3, row3, val3, 1)
-    assert e.value.code == m.MACE_E_PARTITION
-
-
-def test_rejects_three_channel_footprint():
+        m.check_layout(g2.nx, g2.ny, g2.n_views, g2.n_channels, cp3, row3, val3, 1, format=1)
+    assert e.value.code == m.MACE_E_ARG
+    with pytest.raises(m.MaceError) as e:  # FP16 values need the compact records
+        m.check_layout(g2.nx, g2.ny, g2.n_views, g2.n_channels, cp3, row3, val3, 1, precision=1)
+    assert e.value.code == m.MACE_E_ARG
     # channel spacing 0.4 mm: a 1 mm pixel covers up to 4 channels per view
-    import paper_1911_09278_amd as m
     g = mi.Geometry(8, 8, 6, 40, pix=1.0, chan=0.4)
     cp, row, val = mi.system_matrix(g)
+    assert m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2) > 0
     with pytest.raises(m.MaceError) as e:
-        m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2)
+        m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, format=1)
     assert e.value.code == m.MACE_E_MATRIX
+    # super-voxels of 16 and 32 pixels
+    g3 = mi.Geometry(40, 40, 48, 60)
+    cp4, row4, val4 = mi.system_matrix(g3)
+    for S in (16, 32):
+        assert m.check_layout(g3.nx, g3.ny, g3.n_views, g3.n_channels, cp4, row4, val4, 2,
+                              sv_size=S) > 0
+
+
+GENERAL_CASES = [
+    # geometry, agents, super-voxel side
+    (mi.Geometry(24, 24, 30, 64, pix=1.0, chan=0.4), 2, 4),   # 0.4 mm channels
+    (mi.Geometry(20, 22, 24, 90, pix=1.0, chan=0.3), 3, 8),   # up to 6 channels per view
+    (mi.Geometry(16, 16, 720, 24), 1, 4),                     # 720 views, one agent
+    (mi.Geometry(36, 36, 48, 56), 4, 16), (mi.Geometry(40, 33, 48, 60), 2, 32),
+    (mi.Geometry(24, 24, 4, 8), 4, 8),                        # empty columns
+]
+
+
+@pytest.mark.parametrize("case", GENERAL_CASES,
+                         ids=lambda c: f"{c[0].nx}x{c[0].ny}v{c[0].n_views}c{c[0].chan}_N{c[1]}_S{c[2]}")
+def test_general_layout_indices_in_bounds(case):
+    import paper_1911_09278_amd as m
+    g, N, S = case
+    cp, row, val = mi.system_matrix(g)
+    lds = m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=S,
+                         format=2)
+    assert 0 < lds <= 160 * 1024
 
 
 LAYOUT_CASES = [
