@@ -51,6 +51,7 @@ extern "C" {
 #define MACE_E_NOMEM (-4)     /* device or host memory exhausted */
 #define MACE_E_HIP (-5)       /* HIP runtime error */
 #define MACE_E_NONFINITE (-6) /* the iteration produced a non-finite residual */
+#define MACE_E_CANCELLED (-7) /* a served scan was cancelled */
 #define MACE_W_MAXITER 1      /* max_iters reached before tol; x_out written */
 
 typedef struct mace_system mace_system;
@@ -160,6 +161,22 @@ int mace_load_system(const mace_geom* geom, const int64_t* col_ptr, const int32_
 int mace_solve(mace_system* sys, const float* y, const float* lambda, const mace_prior* prior,
                double rho, double sigma, int32_t sweeps, int32_t max_iters, double tol,
                const float* w_init, float* x_out, mace_info* info);
+
+/*
+ * Resume a solve from a checkpoint.  The state Algorithm 1 carries from one
+ * Mann iteration to the next is (w, X): the agents' Mann variables and the
+ * agents' partial-update states X_i, which each ICD pass starts from.
+ * mace_get_state returns both after a solve; mace_solve_resume continues
+ * from w0 = w, X0 = X ([n_agents * nx * ny] each, host), rebuilding every
+ * agent's error sinogram e = y - A X_i, for up to max_iters further
+ * iterations.  Resuming a run after k iterations reproduces the uninterrupted
+ * run to FP32 rounding (the rebuilt e differs from the carried one in the
+ * summation order only).  Other arguments, results and errors as mace_solve.
+ */
+int mace_solve_resume(mace_system* sys, const float* y, const float* lambda,
+                      const mace_prior* prior, double rho, double sigma, int32_t sweeps,
+                      int32_t max_iters, double tol, const float* w0, const float* X0,
+                      float* x_out, mace_info* info);
 
 /*
  * Partial-update MACE with a plug-and-play prior (Algorithm 3, Sec. III):
@@ -292,17 +309,20 @@ typedef struct {
   double ms_per_iter;  /* HIP-event time of one Mann iteration */
   double residual;     /* r_k after the timed iterations */
   int32_t status;      /* MACE_OK or MACE_E_NONFINITE */
+  int32_t format;      /* record format of the candidate (1 compact, 2 general) */
 } mace_tune_result;
 
 /*
  * Autotuner of the launch configuration for one geometry: for super-voxel
- * side S in {4, 8} (those whose band fits in LDS; only base->sv_size if it
- * is 4 or 8) and rows_per_agent in {P/4, P/2, P} below the automatic P (only
+ * side S in {4, 8, 16, 32} (those whose band fits in LDS; 16 and 32 in the
+ * general records, FP32 values only; only base->sv_size if it is set) and
+ * rows_per_agent in {P/4, P/2, P} below the automatic P (only
  * base->rows_per_agent if it is set), loads the system, solves a synthetic
  * scan (uniform 0.02/mm image, 1e4 photons, q-GGMRF prior) for `iters` timed
  * Mann iterations and keeps the fastest time per iteration among candidates
  * whose residual is within 1.5x of the best.  All candidates have the same
- * fixed point (the MAP image), so they are compared at equal accuracy.  *best = *base with sv_size and rows_per_agent chosen; results
+ * fixed point (the MAP image), so they are compared at equal accuracy.
+ * *best = *base with sv_size, rows_per_agent and format chosen; results
  * (optional, up to max_results) receive every candidate, *n_results their
  * number.  Results are cached per geometry, matrix, partition and precision
  * for the life of the process.  mace_load_system with sv_size = -1 calls it.
@@ -367,6 +387,13 @@ int mace_server_submit(mace_server* srv, int32_t system_idx, const float* y, con
  * MACE_W_MAXITER, or an error such as MACE_E_NOMEM / MACE_E_NONFINITE). */
 int mace_server_wait(mace_server* srv, int64_t ticket, float* x_out, mace_info* info,
                      double* latency_s);
+
+/* Cancels a submitted scan: one still waiting for admission leaves the queue
+ * at once; one in flight is released, with its slot and memory, after the
+ * Mann iteration running now.  Its mace_server_wait then returns
+ * MACE_E_CANCELLED without an image.  A scan that has finished already is
+ * left as it is (MACE_OK).  Errors: MACE_E_ARG (unknown ticket). */
+int mace_server_cancel(mace_server* srv, int64_t ticket);
 
 /* Counters of the server; returns MACE_OK or the server's failure code. */
 int mace_server_stats(mace_server* srv, mace_server_counters* out);

@@ -23,6 +23,7 @@ MACE_E_PARTITION = -3
 MACE_E_NOMEM = -4
 MACE_E_HIP = -5
 MACE_E_NONFINITE = -6
+MACE_E_CANCELLED = -7
 MACE_W_MAXITER = 1
 
 
@@ -60,7 +61,7 @@ class Info(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("sv_size", ctypes.c_int32), ("rows_per_agent", ctypes.c_int32),
                 ("ms_per_iter", ctypes.c_double), ("residual", ctypes.c_double),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("format", ctypes.c_int32)]
 
 
 class ServerCounters(ctypes.Structure):
@@ -80,6 +81,8 @@ def _load():
     L.mace_load_system.restype = ctypes.c_int
     L.mace_solve.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, P(Info)]
     L.mace_solve.restype = ctypes.c_int
+    L.mace_solve_resume.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, vp, P(Info)]
+    L.mace_solve_resume.restype = ctypes.c_int
     L.mace_solve_pnp.argtypes = [vp, vp, vp, d, d, i32, i32, d, i32, vp, P(Info)]
     L.mace_solve_pnp.restype = ctypes.c_int
     L.mace_solve_dev.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, P(Info), vp]
@@ -114,6 +117,8 @@ def _load():
     L.mace_server_submit.restype = ctypes.c_int
     L.mace_server_wait.argtypes = [vp, i64, vp, P(Info), P(d)]
     L.mace_server_wait.restype = ctypes.c_int
+    L.mace_server_cancel.argtypes = [vp, i64]
+    L.mace_server_cancel.restype = ctypes.c_int
     L.mace_server_stats.argtypes = [vp, P(ServerCounters)]
     L.mace_server_stats.restype = ctypes.c_int
     L.mace_server_destroy.argtypes = [vp]
@@ -142,7 +147,8 @@ EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_pnp", "mace_solve_dev"
             "mace_server_submit", "mace_server_wait", "mace_server_stats", "mace_server_destroy",
             "mace_autotune", "mace_get_config",
             "mace_free_system", "mace_last_error", "mace_test_fail_alloc",
-            "mace_set_fp32_tail")
+            "mace_set_fp32_tail",
+            "mace_solve_resume", "mace_server_cancel")
 
 
 def last_error() -> str:
@@ -207,7 +213,7 @@ def autotune(nx, ny, n_views, n_channels, col_ptr, row, val, n_agents, view_to_a
     table = [{f: getattr(res[i], f) for f, _ in TuneResult._fields_}
              for i in range(min(nres.value, 16))]
     return {"sv_size": best.sv_size, "rows_per_agent": best.rows_per_agent,
-            "ms_per_iter": ms.value, "table": table}
+            "format": best.format, "ms_per_iter": ms.value, "table": table}
 
 
 class System:
@@ -273,6 +279,26 @@ class System:
         rc = _lib.mace_solve(self._h, _ptr(yy), _ptr(ll), ctypes.byref(prior), float(rho),
                              float(sigma), int(sweeps), int(max_iters), float(tol), _ptr(wi),
                              _ptr(x), ctypes.byref(info))
+        _check(rc)
+        return x, info
+
+    def solve_resume(self, y, lam, prior: Prior, rho, sigma, max_iters, w0, X0, tol=0.0,
+                     sweeps=1):
+        """Continue a solve from a checkpoint (w0, X0) of state(); returns
+        (x, info)."""
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        ll = np.ascontiguousarray(lam, dtype=np.float32)
+        ww = np.ascontiguousarray(w0, dtype=np.float32).reshape(-1)
+        XX = np.ascontiguousarray(X0, dtype=np.float32).reshape(-1)
+        if yy.size != self.n_rows or ll.size != self.n_rows:
+            raise ValueError("y / lambda have the wrong size")
+        if ww.size != self.N * self.n or XX.size != self.N * self.n:
+            raise ValueError("w0 / X0 have the wrong size")
+        x = np.empty(self.n, dtype=np.float32)
+        info = Info()
+        rc = _lib.mace_solve_resume(self._h, _ptr(yy), _ptr(ll), ctypes.byref(prior), float(rho),
+                                    float(sigma), int(sweeps), int(max_iters), float(tol),
+                                    _ptr(ww), _ptr(XX), _ptr(x), ctypes.byref(info))
         _check(rc)
         return x, info
 
@@ -412,6 +438,10 @@ class Server:
         _check(_lib.mace_server_wait(self._h, int(ticket), _ptr(x), ctypes.byref(info),
                                      ctypes.byref(lat)))
         return x, info, float(lat.value)
+
+    def cancel(self, ticket):
+        """Cancel a submitted scan (see mace_server_cancel)."""
+        _check(_lib.mace_server_cancel(self._h, int(ticket)))
 
     def stats(self) -> dict:
         c = ServerCounters()

@@ -31,7 +31,7 @@ struct TuneKey {
 };
 
 struct TuneEntry {
-  int sv_size, rows_per_agent;
+  int sv_size, rows_per_agent, format;
   double ms;
   std::vector<mace_tune_result> table;
 };
@@ -79,6 +79,7 @@ extern "C" int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, cons
       *best = opts;
       best->sv_size = it->second.sv_size;
       best->rows_per_agent = it->second.rows_per_agent;
+      best->format = it->second.format;
       if (best_ms_per_iter) *best_ms_per_iter = it->second.ms;
       const int nr = (int)it->second.table.size();
       if (results)
@@ -103,14 +104,17 @@ extern "C" int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, cons
   const double sigma = 0.05 / std::max(geom->nx, geom->ny);
   std::vector<mace_tune_result> table;
   std::vector<float> x(n);
-  for (int S : {4, 8}) {
+  for (int S : {4, 8, 16, 32}) {
     if (opts.sv_size > 0 && opts.sv_size != S) continue;  // the caller fixed S
+    // sides 16 and 32 exist in the general records only (FP32 values)
+    if (S >= 16 && (opts.precision == 1 || opts.format == 1)) continue;
     mace_opts o = opts;
     o.sv_size = S;
     o.rows_per_agent = 0;
+    if (S >= 16) o.format = 2;
     mace_system* sys = nullptr;
     int rc = mace_load_system(geom, col_ptr, row_idx, val, n_agents, view_to_agent, &o, &sys);
-    if (rc == MACE_E_ARG && S == 8) continue;  // LDS too small for this S
+    if (rc == MACE_E_ARG && S > 4) continue;  // LDS too small for this S
     if (rc) return rc;
     if (y.empty()) make_scan();
     // candidates up to the automatic value, which is already capped where
@@ -144,6 +148,7 @@ extern "C" int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, cons
       mace_tune_result tr{};
       tr.sv_size = S;
       tr.rows_per_agent = P;
+      tr.format = sys->format == 1 ? 2 : 1;
       tr.ms_per_iter = info.iters > 0 ? info.iter_ms / info.iters : 0.0;
       tr.residual = info.residual;
       tr.status = rc < 0 ? rc : MACE_OK;
@@ -165,11 +170,13 @@ extern "C" int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, cons
   *best = opts;
   best->sv_size = table[bi].sv_size;
   best->rows_per_agent = table[bi].rows_per_agent;
+  best->format = table[bi].format;
   if (best_ms_per_iter) *best_ms_per_iter = table[bi].ms_per_iter;
   if (results)
     for (int i = 0; i < std::min((int)table.size(), (int)max_results); ++i) results[i] = table[i];
   if (n_results) *n_results = (int)table.size();
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = TuneEntry{best->sv_size, best->rows_per_agent, table[bi].ms_per_iter, table};
+  g_tune_cache[key] = TuneEntry{best->sv_size, best->rows_per_agent, best->format,
+                               table[bi].ms_per_iter, table};
   return MACE_OK;
 }

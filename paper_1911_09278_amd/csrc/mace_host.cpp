@@ -774,7 +774,10 @@ static int build_layout(mace_system* s, const int64_t* cp, const int32_t* row, c
     rc = repack(s, cp, row, val, hp);
     if (rc == MACE_OK) rc = check_pack(s, hp);
     if (rc == MACE_OK) rc = pick_rows_per_block(s);
-    if (rc != MACE_E_MATRIX || fmt_req == 1 || s->precision == 1) return rc;
+    if (rc != MACE_E_MATRIX || fmt_req == 1) return rc;
+    if (s->precision == 1)
+      return fail(MACE_E_MATRIX, "FP16 matrix values need the compact records, and %s",
+                  std::string(last_error_text()).c_str());
     hp = HostPack{};  // not representable in the compact records
   }
   if (s->precision == 1)

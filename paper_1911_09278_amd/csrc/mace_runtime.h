@@ -181,7 +181,8 @@ void release_slot(Batch& b, int idx);
 // prec: the matrix values the slot reads (-1: the system's precision).
 int write_slot(mace_system* s, Batch& b, int i, int active, hipStream_t st, int prec = -1);
 int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam,
-               const float* w_init, const SvArgs& base, hipStream_t st);
+               const float* w_init, const SvArgs& base, hipStream_t st,
+               const float* X_init = nullptr);
 int refresh_slots(mace_system* s, Batch& b, int n_slots, const Schedule* sch, const SvArgs& base,
                   hipStream_t st);
 // Switches slot i to the FP32 matrix values (theta2 and e rebuilt with them).

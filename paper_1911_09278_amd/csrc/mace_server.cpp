@@ -40,6 +40,7 @@ struct Request {
   mace_info info{};
   int status = MACE_OK;
   bool done = false;
+  std::atomic<bool> cancel{false};  // set by mace_server_cancel while in flight
 };
 
 // Scans of one system that share the solver parameters (prior, rho, sigma,
@@ -207,7 +208,9 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
       if (tail && !in16) ++g->tail_iters[i];
       const double res = g->hlast[i];
       int status = -100;
-      if (!std::isfinite(res))
+      if (r->cancel.load())
+        status = MACE_E_CANCELLED;
+      else if (!std::isfinite(res))
         status = MACE_E_NONFINITE;
       else if (r->tol > 0 && res < r->tol)
         status = MACE_OK;
@@ -224,9 +227,11 @@ int mace_server::tick(int k, std::vector<std::pair<Group*, int>>& admitted) {
         continue;
       }
       if (status == -100) continue;
-      r->x.resize(s->n);
-      HIP_OK(hipMemcpyAsync(r->x.data(), g->batch.scan[i]->wbar.p, sizeof(float) * s->n,
-                            hipMemcpyDeviceToHost, st));
+      if (status != MACE_E_CANCELLED) {
+        r->x.resize(s->n);
+        HIP_OK(hipMemcpyAsync(r->x.data(), g->batch.scan[i]->wbar.p, sizeof(float) * s->n,
+                              hipMemcpyDeviceToHost, st));
+      }
       int rc = write_slot(s, g->batch, i, 0, st);
       if (rc) return rc;
       r->status = status;
@@ -437,9 +442,35 @@ extern "C" int mace_server_wait(mace_server* sv, int64_t ticket, float* x_out, m
   sv->reqs.erase(it);
   if (status < 0) {
     if (status == MACE_E_NOMEM) return fail(status, "the scan's state exceeds the HBM budget");
+    if (status == MACE_E_CANCELLED) return fail(status, "the scan was cancelled");
     return fail(status, "scan failed: %s", text.c_str());
   }
   return status;
+}
+
+extern "C" int mace_server_cancel(mace_server* sv, int64_t ticket) {
+  if (!sv) return fail(MACE_E_ARG, "NULL server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return fail(MACE_E_ARG, "unknown ticket %lld", (long long)ticket);
+  Request* r = it->second.get();
+  if (r->done) return MACE_OK;  // finished already: its result stands
+  auto pit = std::find(sv->pending.begin(), sv->pending.end(), r);
+  if (pit != sv->pending.end()) {
+    // not admitted yet: it leaves the queue now
+    sv->pending.erase(pit);
+    r->status = MACE_E_CANCELLED;
+    r->info.status = MACE_E_CANCELLED;
+    r->t_done = Clock::now();
+    r->done = true;
+    ++sv->completed;
+    sv->cv_done.notify_all();
+    sv->cv_work.notify_all();
+    return MACE_OK;
+  }
+  // in flight: its worker releases the slot after the current iteration
+  r->cancel.store(true);
+  return MACE_OK;
 }
 
 extern "C" int mace_server_stats(mace_server* sv, mace_server_counters* out) {

@@ -171,10 +171,11 @@ uint64_t args_key(const SvArgs& a) {
 namespace mace {
 
 // Theta2 = sum_r A_rs^2 Lambda_r and, from y and w_init, the initial state of
-// slot i: w = w_init (or 0), X = G(w), e = y - A X (y, lam: device, global
-// row order).  The slot's table entry is written and switched on.
+// slot i: w = w_init (or 0), X = G(w) -- or X = X_init when a solve is
+// resumed from a checkpoint of (w, X) --, e = y - A X (y, lam: device,
+// global row order).  The slot's table entry is written and switched on.
 int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam,
-               const float* w_init, const SvArgs& base, hipStream_t st) {
+               const float* w_init, const SvArgs& base, hipStream_t st, const float* X_init) {
   ScanSlot& q = *b.scan[i];
   const int64_t nrow = (int64_t)s->N * s->estride;
   HIP_OK(launch_gather_rows(q.yb.p, y, s->row_src.p, nrow, st));
@@ -186,6 +187,7 @@ int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam
   else
     HIP_OK(launch_fill(q.w.p, 0.f, nimg, st));
   HIP_OK(launch_broadcast_mean(q.w.p, q.wbar.p, q.X.p, s->N, s->n, st));
+  if (X_init) HIP_OK(launch_copy(q.X.p, X_init, nimg, st));
   HIP_OK(hipMemsetAsync(q.counter.p, 0, 2 * sizeof(int), st));
   HIP_OK(hipMemsetAsync(b.lastres.p + i, 0, sizeof(double), st));
   int rc = write_slot(s, b, i, 1, st);
@@ -200,7 +202,7 @@ int start_slot(mace_system* s, Batch& b, int i, const float* y, const float* lam
   a.fp16 = b.htable[i].prec;
   rc = launch_phases(s, one, a, kTheta2, st, b.table.p + i);
   if (rc) return rc;
-  if (w_init) {
+  if (w_init || X_init) {
     rc = launch_phases(s, one, a, kRefresh, st, b.table.p + i);
     if (rc) return rc;
   }
@@ -316,6 +318,7 @@ struct BatchIO {
   const float* w_init;
   float* x_out;
   mace_info* info;
+  const float* X_init = nullptr;  // resume: the agents' states of a checkpoint
 };
 
 // Partial-update MACE (Algorithm 1) for `n` scans of this geometry at once.
@@ -357,7 +360,7 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
     a.hpass = hpass;
   }
   for (int i = 0; i < n; ++i) {
-    rc = start_slot(s, b, i, io[i].y, io[i].lam, io[i].w_init, a, st);
+    rc = start_slot(s, b, i, io[i].y, io[i].lam, io[i].w_init, a, st, io[i].X_init);
     if (rc) return rc;
   }
   for (int i = n; i < (int)b.htable.size(); ++i)
@@ -530,6 +533,27 @@ extern "C" int mace_solve(mace_system* s, const float* y, const float* lam, cons
   if (w_init) HIP_OK(dw.upload(w_init, nimg));
   HIP_OK(dx.alloc(s->n));
   BatchIO io{dy.p, dl.p, w_init ? dw.p : nullptr, dx.p, info};
+  int rc = solve_batch_impl(s, 1, &io, pr, rho, sigma, sweeps, max_iters, tol, nullptr);
+  if (rc < 0 && rc != MACE_E_NONFINITE) return rc;
+  const std::string saved = last_error_text();
+  HIP_OK(hipMemcpy(x_out, dx.p, sizeof(float) * s->n, hipMemcpyDeviceToHost));
+  if (rc == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "%s", saved.c_str());
+  return rc;
+}
+
+extern "C" int mace_solve_resume(mace_system* s, const float* y, const float* lam,
+                                 const mace_prior* pr, double rho, double sigma, int32_t sweeps,
+                                 int32_t max_iters, double tol, const float* w0, const float* X0,
+                                 float* x_out, mace_info* info) {
+  if (!s || !y || !lam || !w0 || !X0 || !x_out) return fail(MACE_E_ARG, "NULL argument");
+  const size_t m = (size_t)s->n_views * s->n_ch, nimg = (size_t)s->N * s->n;
+  DevBuf<float> dy, dl, dw, dX, dx;
+  HIP_OK(dy.upload(y, m));
+  HIP_OK(dl.upload(lam, m));
+  HIP_OK(dw.upload(w0, nimg));
+  HIP_OK(dX.upload(X0, nimg));
+  HIP_OK(dx.alloc(s->n));
+  BatchIO io{dy.p, dl.p, dw.p, dx.p, info, dX.p};
   int rc = solve_batch_impl(s, 1, &io, pr, rho, sigma, sweeps, max_iters, tol, nullptr);
   if (rc < 0 && rc != MACE_E_NONFINITE) return rc;
   const std::string saved = last_error_text();

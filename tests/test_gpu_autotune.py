@@ -1,8 +1,9 @@
 """GPU tests of the launch-configuration autotuner.
 
 The tuner times candidate (super-voxel side, rows per agent) pairs on a
-synthetic scan and keeps the fastest.  Checked here: the table covers both
-super-voxel sides, the choice is the fastest finite candidate, a second call
+synthetic scan and keeps the fastest.  Checked here: the table covers the
+super-voxel sides 4 and 8 (compact records) and 16 and 32 (general records),
+the choice is the fastest finite candidate, a second call
 is served from the cache, and a system loaded with sv_size = -1 runs the
 chosen configuration and still reaches the MAP image of the quadratic prior
 (dense Cholesky, NRMSE <= 1e-4 -- every candidate has the same fixed point).
@@ -36,7 +37,8 @@ def test_autotune_choice_cache_and_fixed_point(m):
     t1 = time.perf_counter()
     print(res, f"{t1 - t0:.2f} s", flush=True)
     table = res["table"]
-    assert {r["sv_size"] for r in table} == {4, 8}
+    # sides 4 and 8 in the compact records, 16 and 32 in the general ones
+    assert {(r["sv_size"], r["format"]) for r in table} == {(4, 1), (8, 1), (16, 2), (32, 2)}
     ok = [r for r in table if r["status"] == m.MACE_OK]
     assert ok and all(np.isfinite(r["residual"]) for r in ok)
     fastest = min(ok, key=lambda r: r["ms_per_iter"])
@@ -50,7 +52,8 @@ def test_autotune_choice_cache_and_fixed_point(m):
     # a system loaded with sv_size = -1 runs the tuned configuration
     sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=-1)
     cfg = sysm.config
-    assert (cfg["sv_size"], cfg["rows_per_agent"]) == (res["sv_size"], res["rows_per_agent"])
+    assert (cfg["sv_size"], cfg["rows_per_agent"], cfg["format"]) == \
+        (res["sv_size"], res["rows_per_agent"], res["format"])
     s = mi.scan(g, 1912)
     sx, sigma = 0.001, 5e-4
     x, info = sysm.solve(s.y, s.lam, m.make_prior(0, sx), 0.8, sigma, 6000, tol=1e-6)

@@ -173,3 +173,36 @@ def test_fp16_system_served_beside_fp32(m):
         assert info.status == m.MACE_OK and info.residual < TOL
         assert _nrmse(x, xa) <= 1e-4
         assert _nrmse(x, xmap) <= (1e-3 if k == 0 else 1e-4)
+
+
+def test_cancel_waiting_and_running_scans(m):
+    """Cancellation: with room for one scan at a time, a scan still in the
+    queue leaves it at once and one in flight is released after its current
+    iteration; both report MACE_E_CANCELLED.  The other scans run to their
+    tolerance and equal their results alone (NRMSE <= 1e-4), and the budget
+    is never exceeded."""
+    sysm, _ = _system(m, GA)
+    prior = m.make_prior(0, SX)
+    scans = [mi.scan(GA, 71 + i) for i in range(5)]
+    alone = [sysm.solve(s.y, s.lam, prior, 0.8, SIGMA, 4000, tol=TOL)[0] for s in scans]
+    budget = sysm.scan_bytes + sysm.scan_bytes // 2  # one scan in flight
+    srv = m.Server([sysm], hbm_budget_bytes=budget)
+    # scan 0 runs for a long time (no tolerance), 1-4 wait behind it
+    t_long = srv.submit(0, scans[0].y, scans[0].lam, prior, 0.8, SIGMA, 0.0, 200000)
+    tks = [srv.submit(0, s.y, s.lam, prior, 0.8, SIGMA, TOL, 4000) for s in scans[1:]]
+    srv.cancel(tks[1])  # waiting: leaves the queue
+    with pytest.raises(m.MaceError) as e:
+        srv.wait(tks[1], GA.n)
+    assert e.value.code == m.MACE_E_CANCELLED
+    time.sleep(0.2)
+    srv.cancel(t_long)  # running: released after its current iteration
+    with pytest.raises(m.MaceError) as e:
+        srv.wait(t_long, GA.n)
+    assert e.value.code == m.MACE_E_CANCELLED
+    for i in (0, 2, 3):
+        x, info, _ = srv.wait(tks[i], GA.n)
+        assert info.status == m.MACE_OK
+        assert _nrmse(x, alone[i + 1]) <= 1e-4, i
+    st = srv.stats()
+    assert st["completed"] == 5 and st["peak_bytes"] <= budget and st["in_flight"] == 0
+    srv.close()
