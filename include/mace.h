@@ -210,6 +210,33 @@ int mace_solve_dev(mace_system* sys, const float* y, const float* lambda,
                    int32_t max_iters, double tol, const float* w_init, float* x_out,
                    mace_info* info, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): mace_solve_dev
+ * with the scan's working state (error sinogram, weights, agent images, Mann
+ * state, theta2, residual partials, slot descriptor) in a static workspace
+ * of mace_noalloc_capacity() bytes (16 MiB) per GPU, held from the first
+ * load on that GPU until the process ends.  The call allocates no device or
+ * pinned memory and creates no stream, event or graph; the system's
+ * matrix, schedule and the workspace's address were set up by
+ * mace_load_system.  Same arguments, results and errors as mace_solve_dev
+ * (y, lambda, w_init, x_out in device memory); it runs the same kernels
+ * eagerly on `stream` (NULL = default stream), after the work already queued
+ * there, and returns after they have finished.  A system whose scan state
+ * does not fit the workspace (e.g. 256x256 with 8 agents and 360 views
+ * fits; 512x512 with 16 agents does not) is rejected with MACE_E_NOMEM
+ * before any launch.  Every call on a GPU uses that GPU's one workspace, and
+ * each call clears what must start at zero: calls that overlap in time on
+ * one GPU (from several host threads or streams) race and must not be
+ * made.
+ */
+int mace_solve_dev_noalloc(mace_system* sys, const float* y, const float* lambda,
+                           const mace_prior* prior, double rho, double sigma, int32_t sweeps,
+                           int32_t max_iters, double tol, const float* w_init, float* x_out,
+                           mace_info* info, void* stream);
+
+/* Bytes of the static workspace of mace_solve_dev_noalloc on each GPU. */
+int64_t mace_noalloc_capacity(void);
 
 /*
  * Batched partial-update MACE: n_scans independent scans of this geometry

@@ -87,6 +87,11 @@ def _load():
     L.mace_solve_pnp.restype = ctypes.c_int
     L.mace_solve_dev.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, P(Info), vp]
     L.mace_solve_dev.restype = ctypes.c_int
+    L.mace_solve_dev_noalloc.argtypes = [vp, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp,
+                                         P(Info), vp]
+    L.mace_solve_dev_noalloc.restype = ctypes.c_int
+    L.mace_noalloc_capacity.argtypes = []
+    L.mace_noalloc_capacity.restype = i64
     L.mace_solve_batch.argtypes = [vp, i32, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp]
     L.mace_solve_batch.restype = ctypes.c_int
     L.mace_solve_batch_dev.argtypes = [vp, i32, vp, vp, P(Prior), d, d, i32, i32, d, vp, vp, vp]
@@ -147,8 +152,13 @@ EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_pnp", "mace_solve_dev"
             "mace_server_submit", "mace_server_wait", "mace_server_stats", "mace_server_destroy",
             "mace_autotune", "mace_get_config",
             "mace_free_system", "mace_last_error", "mace_test_fail_alloc",
-            "mace_set_fp32_tail",
+            "mace_solve_dev_noalloc", "mace_noalloc_capacity", "mace_set_fp32_tail",
             "mace_solve_resume", "mace_server_cancel")
+
+
+def noalloc_capacity() -> int:
+    """Bytes of the static per-GPU workspace of the allocation-free solve."""
+    return int(_lib.mace_noalloc_capacity())
 
 
 def last_error() -> str:
@@ -327,6 +337,20 @@ class System:
                                  None if w_init_ptr is None else ctypes.c_void_p(w_init_ptr),
                                  ctypes.c_void_p(x_ptr), ctypes.byref(info),
                                  None if stream_ptr is None else ctypes.c_void_p(stream_ptr))
+        _check(rc)
+        return info
+
+    def solve_dev_noalloc(self, y_ptr, lam_ptr, prior: Prior, rho, sigma, max_iters, x_ptr,
+                          tol=0.0, sweeps=1, w_init_ptr=None, stream_ptr=None):
+        """mace_solve_dev without device allocation (static per-GPU
+        workspace); device pointers in, returns info."""
+        info = Info()
+        rc = _lib.mace_solve_dev_noalloc(self._h, ctypes.c_void_p(y_ptr), ctypes.c_void_p(lam_ptr),
+                                         ctypes.byref(prior), float(rho), float(sigma),
+                                         int(sweeps), int(max_iters), float(tol),
+                                         None if w_init_ptr is None else ctypes.c_void_p(w_init_ptr),
+                                         ctypes.c_void_p(x_ptr), ctypes.byref(info),
+                                         None if stream_ptr is None else ctypes.c_void_p(stream_ptr))
         _check(rc)
         return info
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libmace.so")
-SOURCES = ["mace_host.cpp", "mace_solve.cpp", "mace_server.cpp", "mace_autotune.cpp", "mace_kernels.hip", "mace_sweep_s4f32.hip", "mace_sweep_s4f16.hip",
+SOURCES = ["mace_host.cpp", "mace_solve.cpp", "mace_server.cpp", "mace_autotune.cpp", "mace_kernels.hip", "mace_noalloc.hip", "mace_sweep_s4f32.hip", "mace_sweep_s4f16.hip",
            "mace_sweep_s8f32.hip", "mace_sweep_s8f16.hip", "mace_sweep_gen.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -852,6 +852,12 @@ extern "C" int mace_load_system(const mace_geom* geom, const int64_t* col_ptr,
     std::lock_guard<std::mutex> lk(capture_mutex());
     HIP_OK(hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking));
   }
+  // what the allocation-free solve needs: its workspace's address on this
+  // device and the one-scan schedule
+  rc = noalloc_prepare(s->device);
+  if (rc) return rc;
+  if (!get_schedule(s.get(), 1, -1, default_rows_per_agent(s.get())))
+    return fail(MACE_E_HIP, "schedule upload failed");
   *out = s.release();
   g_err.clear();
   return MACE_OK;

@@ -196,4 +196,9 @@ int run_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, co
 // Rows per (scan, agent) when n scans run together (share_gpu: other
 // streams run launches beside them).
 int batch_rows_per_agent(const mace_system* s, int n, bool share_gpu);
+// Allocation-free entry point (mace_noalloc.hip): looks up this device's
+// static workspace once; its capacity and the bytes a scan of s needs there.
+int noalloc_prepare(int device);
+size_t noalloc_capacity();
+size_t noalloc_bytes(const mace_system* s);
 }  // namespace mace
