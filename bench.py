@@ -560,123 +560,113 @@ def equits_to_reach(ks, nrmse, thr, equits_per_iter=1.0):
     return None
 
 
+STUDY_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def load_study_reference():
+    """The converged image x* of the study problem and the centralised
+    baseline's equits, as written by tests/golden/make_study_reference.py
+    (FP64 oracle, centralised ICD to a pass change of 1e-12)."""
+    import hashlib
+    meta = json.load(open(os.path.join(STUDY_DIR, "study256_reference.json")))
+    raw = open(os.path.join(STUDY_DIR, "study256_xstar.f32"), "rb").read()
+    if hashlib.sha256(raw).hexdigest() != meta["xstar_sha256"]:
+        raise RuntimeError("study256_xstar.f32 does not match its reference record")
+    return np.frombuffer(raw, dtype="<f4").astype(np.float64), meta
+
+
 def bench_study(args, m, mi, torch):
-    """Synthetic re-run of the paper's convergence studies (Sec. IV-B) on the
-    scan512 geometry: equits to reach an NRMSE threshold against the
-    converged image x*, for rho = 0.5..0.9 at N = 16 (Table II) and for
-    N = 6..48 view subsets at rho = 0.8 (Fig. 4), with the algorithmic
-    speedup N x equits(N_min) / equits(N) and the matrix bytes each agent
-    holds (Table III's rows).  An agent owns at most 128 views, so at 720
-    views the fewest subsets is N_min = 6 and the speedup is taken relative
-    to it, as Table III takes it relative to its fewest subsets.  x* is a
-    16-agent run of 6000 iterations: the MACE fixed point is the MAP image
-    whatever N (Theorem 1); its distance from the 3000-iteration image is
-    reported beside it.  NRMSE at iteration k comes from a fresh solve
-    of k iterations.  sigma = 1e-4 for every N (one setting for all N, as the
-    paper keeps its parameters fixed across N); at N = 16 and rho = 0.8,
-    sigma = 5e-5 and 2e-4 are run as well.  MACE-PnP (Algorithm 3, H = one
-    binomial pass, sigma = 5e-5) is run for the same N against its own x*
-    (Fig. 5(c)), to NRMSE 1e-2 and 1e-3.  In this small-sigma regime the NRMSE thresholds are 0.3 and
-    0.2: the 1e-2 level is not reached in 400 iterations."""
-    w = mi.WORKLOADS["scan512"]
-    g = w.geom
-    prior = m.make_prior(w.prior_kind, w.sigma_x, w.p, w.q, w.T)
-    thresholds = (0.3, 0.2)
-    pnp_thresholds = (1e-2, 1e-3)
-    # the longest curve: --iters when given, else 400 (the scan default of 60
-    # is far too short for these curves)
-    k_max = args.iters if args.iters != 60 else 400
-    agent_counts = (6, 8, 12, 16, 24, 48)
+    """Synthetic re-run of the paper's convergence studies (Sec. IV-B):
+    equits for MACE to reach NRMSE thresholds against the fully converged
+    image x* (Table II: against rho at N = 8; Fig. 4: against the number of
+    view subsets N at rho = 0.8), the speedup N x equits(centralised) /
+    equits(N) of Sec. IV-B, and the system-matrix bytes each agent holds
+    (Table III).  Problem: 256x256, 360 views, 368 channels, q-GGMRF p = 2,
+    q = 1.2, T = 1, sigma_x = 1e-3; x* and the centralised ICD's equits come
+    from the oracle (tests/golden/make_study_reference.py).  One Mann
+    iteration with one ICD pass per agent is one equit.  The NRMSE curve of
+    a run is sampled by stopping it, reading x = mean w, and resuming from
+    the checkpoint (w, X).  Two prox settings: sigma = 2e-4 sqrt(N / 8),
+    which keeps each agent's sigma^2 theta2 -- what bounds the stable range
+    -- the same for every N, and one sigma = 1e-4 for every N."""
+    x_star, meta = load_study_reference()
+    p = meta["problem"]
+    g = mi.Geometry(p["nx"], p["ny"], p["n_views"], p["n_channels"])
+    pr = p["prior"]
+    prior = m.make_prior(pr["kind"], pr["sigma_x"], pr["p"], pr["q"], pr["T"])
+    thresholds = tuple(float(t) for t in meta["centralized_equits"])
+    central = {t: meta["centralized_equits"][t] for t in meta["centralized_equits"]}
+    k_max = args.iters if args.iters != 60 else 3000
     log("study: matrix")
     cp, row, val = mi.system_matrix(g)
-    sc = mi.scan(g, w.seed)
+    sc = mi.scan(g, p["seed"])
+    ref = float(np.linalg.norm(x_star))
     t_start = time.perf_counter()
 
-    def load(n_agents):
-        t = time.perf_counter()
-        s = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, n_agents)
-        s.set_relaxation(args.relax)
-        log(f"study: loaded N={n_agents} in {time.perf_counter() - t:.1f} s")
-        return s
-
-    def curve(s, rho, sigma, x_star, label, pnp=False, thr=thresholds):
+    def curve(sysm, rho, sigma):
+        """NRMSE(x_k, x*) at k = 1, 2, ... (every iteration to 20, then
+        every 2nd, 5th and 10th), through checkpoint / resume."""
         ks, es = [], []
-        ref = float(np.linalg.norm(x_star))
+        k_done, w, X = 0, None, None
         for k in study_grid(k_max):
             try:
-                if pnp:
-                    x, _ = s.solve_pnp(sc.y, sc.lam, rho, sigma, k, h_passes=1)
+                if w is None:
+                    x, _ = sysm.solve(sc.y, sc.lam, prior, rho, sigma, k)
                 else:
-                    x, _ = s.solve(sc.y, sc.lam, prior, rho, sigma, k)
+                    x, _ = sysm.solve_resume(sc.y, sc.lam, prior, rho, sigma, k - k_done, w, X)
+                w, X = sysm.state()
                 e = float(np.linalg.norm(x.astype(np.float64) - x_star)) / ref
-            except m.MaceError as err:  # a diverging iteration
+            except m.MaceError as err:
                 if err.code != m.MACE_E_NONFINITE:
                     raise
                 e = float("inf")
+            k_done = k
             ks.append(k)
             es.append(e if np.isfinite(e) else float("inf"))
-            if not np.isfinite(e) or e > 10.0:
+            if not np.isfinite(e) or e > 10.0 or e < 0.3 * min(thresholds):
                 break
-        log(f"study: {label}: {len(ks)} solves, last k={ks[-1]} NRMSE={es[-1]:.3e}")
         return {"sigma": sigma, "k": ks, "nrmse": es,
-                "equits": {str(t): equits_to_reach(ks, es, t) for t in thr}}
+                "equits": {str(t): equits_to_reach(ks, es, t) for t in thresholds}}
 
-    s = load(16)
-    x_half, _ = s.solve(sc.y, sc.lam, prior, w.rho, 1e-4, 3000)
-    x_star, info = s.solve(sc.y, sc.lam, prior, w.rho, 1e-4, 6000)
-    x_star = x_star.astype(np.float64)
-    drift = float(np.linalg.norm(x_half - x_star) / np.linalg.norm(x_star))
-    log(f"study: x* after {info.iters} iterations, r = {info.residual:.2e}, "
-        f"NRMSE(x_3000, x*) = {drift:.3e}")
-    x_star_info = {"agents": 16, "rho": w.rho, "sigma": 1e-4, "iters": info.iters,
-                   "final_residual": info.residual, "nrmse_3000_vs_6000": drift}
-    xp_half, _ = s.solve_pnp(sc.y, sc.lam, w.rho, 5e-5, 3000, h_passes=1)
-    xp_star, pinfo = s.solve_pnp(sc.y, sc.lam, w.rho, 5e-5, 6000, h_passes=1)
-    xp_star = xp_star.astype(np.float64)
-    pdrift = float(np.linalg.norm(xp_half - xp_star) / np.linalg.norm(xp_star))
-    log(f"study: PnP x* r = {pinfo.residual:.2e}, NRMSE(x_3000, x*) = {pdrift:.3e}")
-    xp_star_info = {"agents": 16, "rho": w.rho, "sigma": 5e-5, "h_passes": 1,
-                    "iters": pinfo.iters, "final_residual": pinfo.residual,
-                    "nrmse_3000_vs_6000": pdrift}
-    s.close()
-    out_sigma, out_pnp = {}, {}
     out_rho, out_n = {}, {}
-    for n_agents in agent_counts:
-        s = load(n_agents)
-        sigma = 1e-4
-        rhos = (0.5, 0.6, 0.7, 0.8, 0.9) if n_agents == 16 else (0.8,)
+    for n_agents in (2, 4, 8, 12, 24):
+        t = time.perf_counter()
+        sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, n_agents)
+        sysm.set_relaxation(args.relax)
+        cfg = sysm.config
+        log(f"study: N={n_agents} loaded in {time.perf_counter() - t:.1f} s "
+            f"(format {cfg['format']}, S {cfg['sv_size']}, rows {cfg['rows_per_agent']})")
+        rhos = (0.5, 0.6, 0.7, 0.8, 0.9) if n_agents == 8 else (0.8,)
+        entry = {"matrix_bytes": sysm.matrix_bytes,
+                 "matrix_bytes_per_agent": sysm.matrix_bytes / n_agents,
+                 "csc_bytes_per_agent": int(cp[-1]) * 8 / n_agents,
+                 "record_format": cfg["format"]}
         for rho in rhos:
-            c = curve(s, rho, sigma, x_star, f"N={n_agents} rho={rho}")
-            if n_agents == 16:
+            c = curve(sysm, rho, 2e-4 * np.sqrt(n_agents / 8.0))
+            log(f"study: N={n_agents} rho={rho}: {c['equits']}")
+            if n_agents == 8:
                 out_rho[str(rho)] = c
-                if rho == 0.8:
-                    out_sigma[str(sigma)] = c
-                    for sg in (5e-5, 2e-4):
-                        out_sigma[str(sg)] = curve(s, rho, sg, x_star,
-                                                   f"N=16 rho=0.8 sigma={sg}")
             if rho == 0.8:
-                c.update({"matrix_bytes": s.matrix_bytes,
-                          "matrix_bytes_per_agent": s.matrix_bytes / n_agents})
-                out_n[str(n_agents)] = c
-        out_pnp[str(n_agents)] = curve(s, 0.8, 5e-5, xp_star, f"PnP N={n_agents}", pnp=True,
-                                       thr=pnp_thresholds)
-        s.close()
-    base = out_n[str(agent_counts[0])]["equits"]
-    for n_agents in agent_counts:
-        c = out_n[str(n_agents)]
-        c["speedup_vs_N6"] = {
-            t: None if base[t] is None or c["equits"][t] is None
-            else n_agents * base[t] / c["equits"][t] for t in base}
-    return {"metric": "MACE convergence study (equits to NRMSE thresholds), 512x512",
+                entry["scaled_sigma"] = c
+                cf = curve(sysm, rho, 1e-4)
+                log(f"study: N={n_agents} rho=0.8 sigma=1e-4: {cf['equits']}")
+                entry["fixed_sigma"] = cf
+        for key in ("scaled_sigma", "fixed_sigma"):
+            eq = entry[key]["equits"]
+            entry[key]["speedup"] = {
+                t: None if eq[t] is None or central[t] is None
+                else n_agents * central[t] / eq[t] for t in eq}
+        out_n[str(n_agents)] = entry
+        sysm.close()
+    return {"metric": "MACE convergence study: equits to NRMSE thresholds against x*, 256x256",
             "unit": "equits", "n_gpus": 1, "data": "synthetic",
-            "config": {"workload": "scan512: 512x512 image, 720 views, 736 channels, "
-                                   "q-GGMRF prior, interleaved view subsets",
-                       "thresholds": list(thresholds), "pnp_thresholds": list(pnp_thresholds),
-                       "k_max": k_max,
+            "config": {"workload": "study256: 256x256 image, 360 views, 368 channels, "
+                                   "q-GGMRF p=2 q=1.2 T=1 sigma_x=1e-3, interleaved view "
+                                   "subsets", "thresholds": list(thresholds), "k_max": k_max,
                        "relaxation": args.relax},
-            "x_star": x_star_info, "vs_rho_N16": out_rho, "vs_N_rho0.8": out_n,
-            "vs_sigma_N16_rho0.8": out_sigma,
-            "pnp_x_star": xp_star_info, "pnp_vs_N_rho0.8": out_pnp,
+            "x_star": {"centralized_icd_passes": meta["passes"],
+                       "grad_ratio": meta["grad_ratio"]},
+            "centralized_equits": central, "vs_rho_N8": out_rho, "vs_N_rho0.8": out_n,
             "elapsed_s": time.perf_counter() - t_start}
 
 

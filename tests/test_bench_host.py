@@ -33,3 +33,27 @@ def test_equits_first_crossing_and_failures():
     # a curve that rises before it crosses takes the crossing sample itself
     assert bench.equits_to_reach([1, 2, 3], [0.1, 0.2, 0.005], 1e-2) > 2
     assert np.isfinite(bench.equits_to_reach([1, 2, 3], [0.01, 0.02, 0.005], 1e-2))
+
+
+def test_study_reference_is_the_map():
+    """The stored x* of the convergence study (written by
+    tests/golden/make_study_reference.py with the oracle) matches its
+    checksum and is the minimiser of f: the oracle's gradient of f at the
+    stored (float32-rounded) image is below 1e-7 of its value at 0."""
+    import mace_inputs as mi
+    import oracle
+    x, meta = bench.load_study_reference()
+    p = meta["problem"]
+    g = mi.Geometry(p["nx"], p["ny"], p["n_views"], p["n_channels"])
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, p["seed"])
+    pr = p["prior"]
+    O = oracle.Oracle(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, s.y, s.lam,
+                      mi.interleaved_partition(g.n_views, 1), pr["kind"], pr["sigma_x"], pr["p"],
+                      pr["q"], pr["T"])
+    g0 = np.abs(O.gradient(np.zeros(g.n))).max()
+    assert np.abs(O.gradient(x)).max() < 1e-7 * g0
+    assert meta["grad_ratio"] < 1e-10
+    c = meta["centralized_equits"]
+    assert all(c[t] is not None for t in c)
+    assert c["0.01"] < c["0.003"] < c["0.001"]
