@@ -84,7 +84,8 @@ class _In(ctypes.Structure):
                 ("prior_kind", ctypes.c_int32),
                 ("sigma_x", ctypes.c_double), ("p", ctypes.c_double), ("q", ctypes.c_double),
                 ("T", ctypes.c_double), ("b_edge", ctypes.c_double),
-                ("b_diag", ctypes.c_double)]
+                ("b_diag", ctypes.c_double), ("nz", ctypes.c_int32),
+                ("b_axial", ctypes.c_double)]
 
 
 _lib = None
@@ -133,10 +134,16 @@ def num_threads() -> int:
 
 
 class Oracle:
-    """One problem: geometry, A (CSC), data y/Lambda, partition and prior."""
+    """One problem: geometry, A (CSC), data y/Lambda, partition and prior.
+
+    Volumes: nz slices of nx x ny pixels measured by the same 2-D matrix,
+    y / lam of shape [nz * n_views * n_ch] (slice-major), images of shape
+    [nz * nx * ny]; b_axial weights the cliques between a voxel and the ones
+    above and below it.  nz = 1 (default) is the 2-D problem."""
 
     def __init__(self, nx, ny, n_views, n_ch, col_ptr, row, val, y, lam, view_agent,
-                 prior_kind, sigma_x, p=2.0, q=2.0, T=1.0, b_edge=None, b_diag=None):
+                 prior_kind, sigma_x, p=2.0, q=2.0, T=1.0, b_edge=None, b_diag=None, nz=1,
+                 b_axial=0.0):
         L = _load()
         if b_edge is None:
             b_edge = 1.0 / (4.0 + 2.0 * np.sqrt(2.0))
@@ -150,12 +157,15 @@ class Oracle:
                       np.ascontiguousarray(view_agent, dtype=np.int32)]
         cp, rw, vl, yy, ll, va = self._keep
         self.nx, self.ny, self.n_views, self.n_ch = int(nx), int(ny), int(n_views), int(n_ch)
-        self.n = self.nx * self.ny
-        self.n_rows = self.n_views * self.n_ch
+        self.nz = int(nz)
+        self.n = self.nx * self.ny * self.nz
+        self.n_rows = self.n_views * self.n_ch * self.nz
+        if yy.size != self.n_rows or ll.size != self.n_rows:
+            raise ValueError("y / lam need nz * n_views * n_ch entries")
         self.N = int(va.max()) + 1
         inp = _In(self.nx, self.ny, self.n_views, self.n_ch, _p(cp), _p(rw), _p(vl), _p(yy),
                   _p(ll), self.N, _p(va), int(prior_kind), float(sigma_x), float(p), float(q),
-                  float(T), float(b_edge), float(b_diag))
+                  float(T), float(b_edge), float(b_diag), self.nz, float(b_axial))
         self._h = L.orc_create(ctypes.byref(inp))
         if not self._h:
             raise ValueError("oracle: bad problem description")

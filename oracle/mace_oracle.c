@@ -47,6 +47,15 @@
  * with ||X^{k+1}|| in the denominator while w^k = 0); it vanishes exactly at a
  * fixed point, where X = G w (proof of Theorem 1).  The loop also stops when
  * r_k is not finite (a diverging run), after recording it.
+ *
+ * Volumes (nz > 1): a stack of nz slices of nx x ny pixels, each slice
+ * measured by the same 2-D matrix A (parallel beam: every ray lies in one
+ * slice), slice z's rows r + z * n_rows.  The prior adds axial cliques
+ * between voxel (z, s) and (z + 1, s) with weight b_axial:
+ *   h(x) = sum_z h_2D(x_z) + sum_{z, s} b_axial rho(x_{z,s} - x_{z+1,s}).
+ * Voxel ids are v = z * nx * ny + s; every array over the image is over the
+ * voxels, every array over the sinogram over the nz stacked sinograms.
+ * nz = 1 is the 2-D problem above.
  */
 #include <math.h>
 #include <stdint.h>
@@ -67,11 +76,14 @@ typedef struct {
   const int32_t* view_agent; /* [n_views] */
   int32_t prior_kind;        /* 0 quadratic, 1 q-GGMRF, 2 none (beta = 0, Sec. III) */
   double sigma_x, p, q, T, b_edge, b_diag;
+  int32_t nz;                /* slices of a volume (1: a 2-D image) */
+  double b_axial;            /* weight of the axial cliques (volumes) */
 } orc_in;
 
 typedef struct {
-  int32_t nx, ny, n_views, n_ch, N;
-  int64_t n, n_rows;
+  int32_t nx, ny, n_views, n_ch, N, nz;
+  int64_t n, n_rows;       /* voxels and sinogram rows of the whole stack */
+  int64_t n2, nr2;         /* pixels and rows of one slice */
   /* per-agent CSC restricted to the agent's rows (global row ids) */
   int64_t** cp;
   int32_t** rw;
@@ -80,7 +92,7 @@ typedef struct {
   double* lam;
   int32_t* row_agent;
   int32_t kind;
-  double sx, p, q, T, be, bd;
+  double sx, p, q, T, be, bd, ba;
 } orc_state;
 
 /* ---------------- prior potential ---------------- */
@@ -114,8 +126,11 @@ static double pot_curv(const orc_state* S, double d) {
          ((1.0 + s) * (1.0 + s));
 }
 
-/* 8-neighbourhood of pixel s: fills nb[] and wt[], returns count. */
-static int neighbours(const orc_state* S, int64_t s, int64_t* nb, double* wt) {
+/* Neighbourhood of voxel v: the 8 in-plane neighbours in its slice and, in
+ * a volume with b_axial > 0, the voxels above and below it; fills nb[] (at
+ * most 10) and wt[], returns the count. */
+static int neighbours(const orc_state* S, int64_t v, int64_t* nb, double* wt) {
+  const int64_t z = v / S->n2, s = v % S->n2;
   int64_t i = s / S->nx, j = s % S->nx;
   int c = 0;
   for (int di = -1; di <= 1; ++di)
@@ -123,10 +138,20 @@ static int neighbours(const orc_state* S, int64_t s, int64_t* nb, double* wt) {
       if (!di && !dj) continue;
       int64_t ii = i + di, jj = j + dj;
       if (ii < 0 || ii >= S->ny || jj < 0 || jj >= S->nx) continue;
-      nb[c] = ii * S->nx + jj;
+      nb[c] = z * S->n2 + ii * S->nx + jj;
       wt[c] = (di && dj) ? S->bd : S->be;
       ++c;
     }
+  if (S->ba > 0) {
+    if (z > 0) {
+      nb[c] = v - S->n2;
+      wt[c++] = S->ba;
+    }
+    if (z + 1 < S->nz) {
+      nb[c] = v + S->n2;
+      wt[c++] = S->ba;
+    }
+  }
   return c;
 }
 
@@ -142,8 +167,12 @@ orc_state* orc_create(const orc_in* in) {
   S->n_views = in->n_views;
   S->n_ch = in->n_ch;
   S->N = in->n_agents;
-  S->n = (int64_t)in->nx * in->ny;
-  S->n_rows = (int64_t)in->n_views * in->n_ch;
+  S->nz = in->nz > 0 ? in->nz : 1;
+  S->n2 = (int64_t)in->nx * in->ny;
+  S->nr2 = (int64_t)in->n_views * in->n_ch;
+  S->n = S->n2 * S->nz;
+  S->n_rows = S->nr2 * S->nz;
+  S->ba = S->nz > 1 ? in->b_axial : 0.0;
   S->kind = in->prior_kind;
   S->sx = in->sigma_x;
   S->p = in->p;
@@ -157,24 +186,25 @@ orc_state* orc_create(const orc_in* in) {
   for (int64_t r = 0; r < S->n_rows; ++r) {
     S->y[r] = in->y ? (double)in->y[r] : 0.0;
     S->lam[r] = in->lam ? (double)in->lam[r] : 0.0;
-    S->row_agent[r] = in->view_agent[r / S->n_ch];
+    S->row_agent[r] = in->view_agent[(r % S->nr2) / S->n_ch];
   }
   int N = S->N;
   S->cp = (int64_t**)calloc(N, sizeof(int64_t*));
   S->rw = (int32_t**)calloc(N, sizeof(int32_t*));
   S->av = (double**)calloc(N, sizeof(double*));
-  for (int a = 0; a < N; ++a) S->cp[a] = (int64_t*)calloc(S->n + 1, sizeof(int64_t));
+  /* the per-agent CSC of the 2-D matrix (slice 0's rows) */
+  for (int a = 0; a < N; ++a) S->cp[a] = (int64_t*)calloc(S->n2 + 1, sizeof(int64_t));
   /* count entries per (agent, column) */
-  for (int64_t s = 0; s < S->n; ++s)
+  for (int64_t s = 0; s < S->n2; ++s)
     for (int64_t t = in->col_ptr[s]; t < in->col_ptr[s + 1]; ++t)
       S->cp[S->row_agent[in->row[t]]][s + 1]++;
   for (int a = 0; a < N; ++a) {
-    for (int64_t s = 0; s < S->n; ++s) S->cp[a][s + 1] += S->cp[a][s];
-    S->rw[a] = (int32_t*)malloc(sizeof(int32_t) * (S->cp[a][S->n] + 1));
-    S->av[a] = (double*)malloc(sizeof(double) * (S->cp[a][S->n] + 1));
+    for (int64_t s = 0; s < S->n2; ++s) S->cp[a][s + 1] += S->cp[a][s];
+    S->rw[a] = (int32_t*)malloc(sizeof(int32_t) * (S->cp[a][S->n2] + 1));
+    S->av[a] = (double*)malloc(sizeof(double) * (S->cp[a][S->n2] + 1));
   }
   int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * N);
-  for (int64_t s = 0; s < S->n; ++s) {
+  for (int64_t s = 0; s < S->n2; ++s) {
     for (int a = 0; a < N; ++a) pos[a] = S->cp[a][s];
     for (int64_t t = in->col_ptr[s]; t < in->col_ptr[s + 1]; ++t) {
       int a = S->row_agent[in->row[t]];
@@ -213,23 +243,25 @@ void orc_set_data(orc_state* S, const float* y, const float* lam) {
 
 /* ---------------- objective pieces ---------------- */
 
-/* e_r = y_r - (A x)_r on the rows of `agent` (on all rows when agent < 0). */
+/* e_r = y_r - (A x)_r on the rows of `agent` (on all rows when agent < 0),
+ * every slice of a volume. */
 void orc_error_sinogram(const orc_state* S, int agent, const double* x, double* e) {
   for (int a = 0; a < S->N; ++a) {
     if (agent >= 0 && a != agent) continue;
     for (int64_t r = 0; r < S->n_rows; ++r)
       if (S->row_agent[r] == a) e[r] = S->y[r];
-    for (int64_t s = 0; s < S->n; ++s)
-      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t)
-        e[S->rw[a][t]] -= S->av[a][t] * x[s];
+    for (int64_t z = 0; z < S->nz; ++z)
+      for (int64_t s = 0; s < S->n2; ++s)
+        for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t)
+          e[z * S->nr2 + S->rw[a][t]] -= S->av[a][t] * x[z * S->n2 + s];
   }
 }
 
 /* h(x): each unordered neighbour pair once. */
 double orc_prior(const orc_state* S, const double* x) {
   double h = 0.0;
-  int64_t nb[8];
-  double wt[8];
+  int64_t nb[10];
+  double wt[10];
   for (int64_t s = 0; s < S->n; ++s) {
     int c = neighbours(S, s, nb, wt);
     for (int k = 0; k < c; ++k)
@@ -274,15 +306,17 @@ void orc_gradient(const orc_state* S, int agent, const double* x, double* g) {
   for (int a = 0; a < S->N; ++a) {
     if (agent >= 0 && a != agent) continue;
     orc_error_sinogram(S, a, x, e);
-    for (int64_t s = 0; s < S->n; ++s)
+    for (int64_t v = 0; v < S->n; ++v) {
+      const int64_t z = v / S->n2, s = v % S->n2;
       for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t) {
-        int32_t r = S->rw[a][t];
-        g[s] -= S->av[a][t] * S->lam[r] * e[r];
+        const int64_t r = z * S->nr2 + S->rw[a][t];
+        g[v] -= S->av[a][t] * S->lam[r] * e[r];
       }
+    }
   }
   double scale = agent < 0 ? 1.0 : 1.0 / S->N;
-  int64_t nb[8];
-  double wt[8];
+  int64_t nb[10];
+  double wt[10];
   for (int64_t s = 0; s < S->n; ++s) {
     int c = neighbours(S, s, nb, wt);
     for (int k = 0; k < c; ++k) g[s] += scale * wt[k] * pot_d1(S, x[s] - x[nb[k]]);
@@ -313,14 +347,16 @@ int orc_icd_pass(const orc_state* S, int agent, double sigma, const double* v,
   int a0 = agent < 0 ? 0 : agent, a1 = agent < 0 ? S->N : agent + 1;
   double pscale = agent < 0 ? 1.0 : 1.0 / S->N;
   double is2 = sigma > 0 ? 1.0 / (sigma * sigma) : 0.0;
-  int64_t nb[8];
-  double wt[8];
+  int64_t nb[10];
+  double wt[10];
   for (int64_t it = 0; it < S->n; ++it) {
-    int64_t s = order ? order[it] : it;
+    /* voxel s of the stack: column sc of A, rows of slice sz */
+    const int64_t s = order ? order[it] : it;
+    const int64_t sz = s / S->n2, sc = s % S->n2, roff = sz * S->nr2;
     double th1 = 0.0, th2 = 0.0;
     for (int a = a0; a < a1; ++a)
-      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t) {
-        int32_t r = S->rw[a][t];
+      for (int64_t t = S->cp[a][sc]; t < S->cp[a][sc + 1]; ++t) {
+        const int64_t r = roff + S->rw[a][t];
         double A = S->av[a][t];
         th1 -= A * S->lam[r] * e[r];
         th2 += A * A * S->lam[r];
@@ -377,8 +413,8 @@ int orc_icd_pass(const orc_state* S, int agent, double sigma, const double* v,
     alpha *= relax;
     z[s] = zs + alpha;
     for (int a = a0; a < a1; ++a)
-      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t)
-        e[S->rw[a][t]] -= S->av[a][t] * alpha;
+      for (int64_t t = S->cp[a][sc]; t < S->cp[a][sc + 1]; ++t)
+        e[roff + S->rw[a][t]] -= S->av[a][t] * alpha;
     if (phi_trace) phi_trace[it] = orc_cost(S, agent, z, v, sigma);
   }
   return 0;
@@ -524,25 +560,28 @@ int orc_centralized_icd(const orc_state* S, double* x, int max_passes, double rt
  * the weighted graph Laplacian of the 8-neighbour cliques: (L_b v)_s =
  * sum_r b_sr (v_s - v_r).  tmp: scratch of n_rows doubles. */
 static void quad_hessian_apply(const orc_state* S, const double* v, double* out, double* tmp) {
-  /* tmp = A v, agent by agent (the agents' rows are disjoint) */
+  /* tmp = A v, agent by agent (the agents' rows are disjoint), slice by slice */
 #pragma omp parallel for schedule(static, 1)
   for (int a = 0; a < S->N; ++a) {
     for (int64_t r = 0; r < S->n_rows; ++r)
       if (S->row_agent[r] == a) tmp[r] = 0.0;
-    for (int64_t s = 0; s < S->n; ++s)
-      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t) tmp[S->rw[a][t]] += S->av[a][t] * v[s];
+    for (int64_t z = 0; z < S->nz; ++z)
+      for (int64_t s = 0; s < S->n2; ++s)
+        for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t)
+          tmp[z * S->nr2 + S->rw[a][t]] += S->av[a][t] * v[z * S->n2 + s];
   }
   const double c = 1.0 / (S->sx * S->sx);
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < S->n; ++s) {
+    const int64_t sz = s / S->n2, sc = s % S->n2;
     double acc = 0.0;
     for (int a = 0; a < S->N; ++a)
-      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t) {
-        int32_t r = S->rw[a][t];
+      for (int64_t t = S->cp[a][sc]; t < S->cp[a][sc + 1]; ++t) {
+        const int64_t r = sz * S->nr2 + S->rw[a][t];
         acc += S->av[a][t] * S->lam[r] * tmp[r];
       }
-    int64_t nb[8];
-    double wt[8];
+    int64_t nb[10];
+    double wt[10];
     int k = neighbours(S, s, nb, wt);
     for (int q = 0; q < k; ++q) acc += c * wt[q] * (v[s] - v[nb[q]]);
     out[s] = acc;
@@ -570,15 +609,16 @@ int orc_map_cg(const orc_state* S, double* x, int max_iters, double rtol, double
   double* tmp = (double*)malloc(sizeof(double) * S->n_rows);
   const double c = 1.0 / (S->sx * S->sx);
   for (int64_t s = 0; s < n; ++s) {
+    const int64_t sz = s / S->n2, sc = s % S->n2;
     double bs = 0.0, ds = 0.0;
     for (int a = 0; a < S->N; ++a)
-      for (int64_t t = S->cp[a][s]; t < S->cp[a][s + 1]; ++t) {
-        int32_t rr = S->rw[a][t];
+      for (int64_t t = S->cp[a][sc]; t < S->cp[a][sc + 1]; ++t) {
+        const int64_t rr = sz * S->nr2 + S->rw[a][t];
         bs += S->av[a][t] * S->lam[rr] * S->y[rr];
         ds += S->av[a][t] * S->av[a][t] * S->lam[rr];
       }
-    int64_t nb[8];
-    double wt[8];
+    int64_t nb[10];
+    double wt[10];
     int k = neighbours(S, s, nb, wt);
     for (int j = 0; j < k; ++j) ds += c * wt[j];
     b[s] = bs;

@@ -109,3 +109,31 @@ def sor_pass_closed_form(H, b, x, v, sigma, omega):
     D = np.diag(np.diag(M))
     rhs = omega * (b + v / sigma ** 2) - (omega * L.T + (omega - 1.0) * D) @ x
     return np.linalg.solve(D + omega * L, rhs)
+
+
+def laplacian3(nx, ny, nz, b_axial, b_edge=B_EDGE, b_diag=B_DIAG):
+    """Weighted graph Laplacian of a stack of nz slices: the 8-neighbour
+    in-plane cliques of every slice and the axial cliques (z, s)-(z+1, s)
+    with weight b_axial; voxel v = z * nx * ny + s."""
+    n = nx * ny
+    L = np.kron(np.eye(nz), laplacian(nx, ny, b_edge, b_diag))
+    P = np.zeros((nz, nz))
+    for z in range(nz - 1):
+        P[z, z] += 1.0
+        P[z + 1, z + 1] += 1.0
+        P[z, z + 1] -= 1.0
+        P[z + 1, z] -= 1.0
+    return L + b_axial * np.kron(P, np.eye(n))
+
+
+def volume_system(A, lam, y, nz):
+    """Block-diagonal data Hessian and right side of a slice stack measured
+    by one 2-D matrix A: H_data = blockdiag(A^T Lambda_z A), b = A^T Lambda_z y_z."""
+    m, n = A.shape
+    H = np.zeros((nz * n, nz * n))
+    b = np.zeros(nz * n)
+    for z in range(nz):
+        lz, yz = lam[z * m:(z + 1) * m], y[z * m:(z + 1) * m]
+        H[z * n:(z + 1) * n, z * n:(z + 1) * n] = A.T @ (lz[:, None] * A)
+        b[z * n:(z + 1) * n] = A.T @ (lz * yz)
+    return H, b

@@ -25,6 +25,8 @@ typedef struct {
   const int32_t* view_agent;
   int32_t prior_kind;
   double sigma_x, p, q, T, b_edge, b_diag;
+  int32_t nz;
+  double b_axial;
 } orc_in;
 typedef struct orc_state orc_state;
 orc_state* orc_create(const orc_in* in);
@@ -56,37 +58,43 @@ int main(void) {
   int32_t* row = malloc(sizeof(int32_t) * nnz);
   float* val = malloc(sizeof(float) * nnz);
   mi_sysmat_fill(&g, cp, row, val);
-  float* y = malloc(sizeof(float) * m);
-  float* lam = malloc(sizeof(float) * m);
-  for (int64_t r = 0; r < m; ++r) {
+  const int nzmax = 3;  /* the last case is a 3-slice volume */
+  float* y = malloc(sizeof(float) * m * nzmax);
+  float* lam = malloc(sizeof(float) * m * nzmax);
+  for (int64_t r = 0; r < m * nzmax; ++r) {
     y[r] = 0.02f * (float)((r * 37) % 11);
     lam[r] = 1000.0f + (float)(r % 7);
   }
   int32_t va[24];
   for (int k = 0; k < g.n_views; ++k) va[k] = k % 3;
   int bad = 0;
-  for (int kind = 0; kind < 3; ++kind) {
+  for (int c = 0; c < 4; ++c) {
+    /* prior kinds 0, 1, 2 on one slice, then a quadratic 3-slice volume */
+    const int kind = c < 3 ? c : 0, nz = c < 3 ? 1 : nzmax;
     orc_in in = {g.nx, g.ny, g.n_views, g.n_ch, cp, row, val, y, lam, 3, va, kind,
-                 0.01, 2.0, 1.2, 1.0, 0.1464466, 0.1035534};
+                 0.01, 2.0, 1.2, 1.0, 0.1464466, 0.1035534, nz, 0.3};
     orc_state* S = orc_create(&in);
-    double* x = calloc(n, sizeof(double));
-    double* v = calloc(n, sizeof(double));
-    double* e = calloc(m, sizeof(double));
-    double* X = calloc(3 * n, sizeof(double));
-    double* gr = calloc(n, sizeof(double));
+    const int64_t nv = n * nz;
+    double* x = calloc(nv, sizeof(double));
+    double* v = calloc(nv, sizeof(double));
+    double* e = calloc(m * nz, sizeof(double));
+    double* X = calloc(3 * nv, sizeof(double));
+    double* gr = calloc(nv, sizeof(double));
     double res[20];
-    for (int64_t s = 0; s < n; ++s) v[s] = 0.01 * (double)(s % 5);
+    for (int64_t s = 0; s < nv; ++s) v[s] = 0.01 * (double)(s % 5);
     orc_error_sinogram(S, 1, x, e);
     for (int mode = 0; mode < 2; ++mode) orc_icd_pass(S, 1, 0.01, v, x, e, NULL, mode, 1.0, NULL);
-    const double c = orc_cost(S, 1, x, v, 0.01);
+    const double cst = orc_cost(S, 1, x, v, 0.01);
     orc_gradient(S, -1, x, gr);
     const int k = orc_mace_solve(S, 0.8, 1e-3, 1, 20, 0.0, NULL, NULL, 0, 0.5, x, X, res);
     orc_prox(S, 0, 1e-3, v, x, 50, 1e-12, 1);
     orc_centralized_icd(S, x, 20, 1e-12, 0);
     double rel = 0.0;
     if (kind == 0) orc_map_cg(S, x, 200, 1e-12, &rel);
-    bad |= !isfinite(c) || !all_finite(gr, n) || !all_finite(x, n) || !all_finite(X, 3 * n) || k != 20;
-    printf("prior %d: cost %g, %d iterations, residual %g, CG residual %g\n", kind, c, k, res[k - 1], rel);
+    bad |= !isfinite(cst) || !all_finite(gr, nv) || !all_finite(x, nv) || !all_finite(X, 3 * nv) ||
+           k != 20;
+    printf("prior %d, %d slice(s): cost %g, %d iterations, residual %g, CG residual %g\n", kind, nz,
+           cst, k, res[k - 1], rel);
     free(x); free(v); free(e); free(X); free(gr);
     orc_destroy(S);
   }

@@ -431,3 +431,96 @@ def test_P7_pnp_fixed_point_is_the_pnp_map(passes):
     assert res["resid"][-1] < 1e-12
     assert np.linalg.norm(res["x"] - xref) <= 1e-10 * np.linalg.norm(xref)
     assert np.abs(res["X"] - res["x"][None, :]).max() <= 1e-10 * np.abs(res["x"]).max()
+
+
+# ---------------- volumes (slice stacks with axial cliques) ----------------
+def _volume(g, nz, seed, N, kind, sx, b_axial, q=2.0):
+    cp, row, val = mi.system_matrix(g)
+    scans = [mi.scan(g, seed + z) for z in range(nz)]
+    y = np.concatenate([s.y for s in scans])
+    lam = np.concatenate([s.lam for s in scans])
+    va = mi.interleaved_partition(g.n_views, N)
+    O = oracle.Oracle(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, y, lam, va, kind, sx,
+                      2.0, q, 1.0, nz=nz, b_axial=b_axial)
+    A = dr.dense_A(g, cp, row, val)
+    return O, A, lam.astype(np.float64), y.astype(np.float64), (cp, row, val), scans, va
+
+
+def test_P2_volume_fixed_point_is_the_dense_map():
+    """A stack of 3 slices with axial cliques: the MACE fixed point equals the
+    minimiser of the volume's quadratic MAP cost, solved densely, and the
+    oracle's CG solve of the same normal equations."""
+    g = mi.Geometry(8, 8, 12, 12)
+    nz, N, sx, ba = 3, 2, 0.004, 0.3
+    O, A, lam, y, _, _, _ = _volume(g, nz, 51, N, 0, sx, ba)
+    H, b = dr.volume_system(A, lam, y, nz)
+    H += dr.laplacian3(g.nx, g.ny, nz, ba) / sx ** 2
+    xmap = np.linalg.solve(H, b)
+    res = O.mace_solve(0.8, 0.005, 20000, tol=1e-13)
+    assert res["resid"][-1] < 1e-13
+    assert np.linalg.norm(res["x"] - xmap) / np.linalg.norm(xmap) < 1e-9
+    xcg, _, rel = O.map_cg(rtol=1e-14)
+    assert np.linalg.norm(xcg - xmap) / np.linalg.norm(xmap) < 1e-10
+
+
+def test_P1_volume_icd_pass_equals_gauss_seidel_closed_form():
+    """One raster ICD pass over the voxels of a volume (slice-major) equals the
+    Gauss-Seidel closed form of eq. (ICDUpdate1) with the volume's agent
+    Hessian (data of the agent's views in every slice, prior / N including
+    the axial cliques)."""
+    g = mi.Geometry(6, 6, 10, 10)
+    nz, N, agent, sx, ba, sigma = 3, 2, 1, 0.01, 0.4, 0.02
+    O, A, lam, y, _, _, va = _volume(g, nz, 61, N, 0, sx, ba)
+    r = dr.agent_rows(g, va, agent)
+    Ai = np.zeros_like(A)
+    Ai[r] = A[r]
+    H, b = dr.volume_system(Ai, lam, y, nz)
+    H += dr.laplacian3(g.nx, g.ny, nz, ba) / (N * sx ** 2)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0, 0.05, nz * g.n)
+    v = rng.uniform(0, 0.05, nz * g.n)
+    z = x.copy()
+    e = O.error_sinogram(x, agent=agent)
+    O.icd_pass(agent, sigma, v, z, e)
+    ref = dr.icd_pass_closed_form(H, b, x, v, sigma)
+    np.testing.assert_allclose(z, ref, rtol=1e-11, atol=1e-14)
+
+
+def test_P6_volume_without_axial_cliques_is_independent_slices():
+    """b_axial = 0: the volume's MACE iterates are each slice's 2-D iterates."""
+    g = mi.Geometry(10, 10, 16, 16)
+    nz, N, sx = 3, 2, 0.003
+    O, A, lam, y, (cp, row, val), scans, va = _volume(g, nz, 71, N, 1, sx, 0.0, q=1.2)
+    res = O.mace_solve(0.8, 0.003, 12, relax=0.5)
+    for zz, s in enumerate(scans):
+        O2 = oracle.Oracle(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, s.y, s.lam, va, 1,
+                           sx, 2.0, 1.2, 1.0)
+        r2 = O2.mace_solve(0.8, 0.003, 12, relax=0.5)
+        np.testing.assert_allclose(res["x"][zz * g.n:(zz + 1) * g.n], r2["x"], rtol=0,
+                                   atol=1e-13 * np.abs(r2["x"]).max())
+
+
+def test_P2_volume_qggmrf_gradient_and_fixed_point():
+    """q-GGMRF volume: the oracle's gradient matches central differences of
+    its cost (axial cliques included) and vanishes at the MACE fixed point,
+    which equals the centralised ICD's."""
+    g = mi.Geometry(8, 8, 12, 12)
+    nz, N, sx, ba = 3, 2, 0.003, 0.5
+    O, A, lam, y, _, _, _ = _volume(g, nz, 81, N, 1, sx, ba, q=1.2)
+    res = O.mace_solve(0.8, 0.003, 20000, tol=1e-13, relax=0.5)
+    assert res["resid"][-1] < 1e-13
+    x = res["x"]
+    xc, _ = O.centralized_icd(rtol=1e-15, max_passes=20000, mode=oracle.MODE_EXACT)
+    assert np.linalg.norm(x - xc) / np.linalg.norm(xc) < 1e-8
+    g0 = np.abs(O.gradient(np.zeros(nz * g.n))).max()
+    assert np.abs(O.gradient(x)).max() < 1e-8 * g0
+    rng = np.random.default_rng(5)
+    xr = x + 1e-3 * rng.standard_normal(x.size)
+    gr = O.gradient(xr)
+    for s in rng.choice(nz * g.n, 6, replace=False):
+        h = 1e-7
+        xp, xm = xr.copy(), xr.copy()
+        xp[s] += h
+        xm[s] -= h
+        fd = (O.cost(xp) - O.cost(xm)) / (2 * h)
+        assert abs(fd - gr[s]) < 1e-4 * (abs(gr[s]) + 1.0)
