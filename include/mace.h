@@ -179,6 +179,33 @@ int mace_solve_resume(mace_system* sys, const float* y, const float* lambda,
                       float* x_out, mace_info* info);
 
 /*
+ * Volume reconstruction: nz slices of nx x ny pixels, each measured by the
+ * system's 2-D matrix A (parallel beam: every ray lies in one slice), with
+ * the 3-D prior that adds to the 8 in-plane cliques of every slice the axial
+ * cliques between voxel (z, s) and (z + 1, s) with weight b_axial:
+ *   h(x) = sum_z h_2D(x_z) + sum_{z,s} b_axial rho(x_{z,s} - x_{z+1,s})
+ * (the MAP cost of eq. (global_obj) over the stacked volume, its prior split
+ * as h / N among the agents as in eq. (local_obj)).  Each agent holds its
+ * views of every slice.  Partial-update MACE (Algorithm 1, Algorithm 2) runs
+ * over the nz * nx * ny voxels: the consensus, the Mann update and the
+ * residual r_k are those of the stacked vectors, and all slices stop
+ * together when r_k < tol.  The agents visit the super-voxels of one colour
+ * in the even slices, then in the odd slices (the axial neighbours a voxel
+ * reads do not change while its slice sweeps).
+ * y, lambda: host, float[nz][n_views * n_channels] (slice z's sinogram in
+ *   global row order); x_out: host, float[nz][nx * ny].
+ * 1 <= nz <= 128; b_axial >= 0 (0: independent slices).  The system must
+ * hold the general records (loaded with mace_opts.format = 2), else
+ * MACE_E_ARG; other arguments, results and errors as mace_solve
+ * (info->residual is the stacked r_k).  The slices occupy scan slots 0 ..
+ * nz - 1: mace_get_slot_state(sys, z, ...) returns slice z's (w, X).
+ */
+int mace_solve_volume(mace_system* sys, int32_t nz, const float* y, const float* lambda,
+                      const mace_prior* prior, double b_axial, double rho, double sigma,
+                      int32_t sweeps, int32_t max_iters, double tol, float* x_out,
+                      mace_info* info);
+
+/*
  * Partial-update MACE with a plug-and-play prior (Algorithm 3, Sec. III):
  * the agents apply partial updates of the proximal maps of their data terms
  * alone (beta = 0, no prior), F_i(v; sqrt(N) sigma) (eq. (FG_PnP)), and the
@@ -288,6 +315,10 @@ int mace_visit_order(const mace_system* sys, int64_t* order);
  * batch), device layout [N][nx*ny], copied to host: w and X (either may be
  * NULL). */
 int mace_get_state(const mace_system* sys, float* w, float* X);
+
+/* As mace_get_state for scan slot `slot` of the last batch or volume solve
+ * (slice z of a volume is slot z).  MACE_E_ARG if the slot holds no state. */
+int mace_get_slot_state(const mace_system* sys, int32_t slot, float* w, float* X);
 
 /* Error sinogram e = y - A X_i of the last solve, every row from its own
  * agent's state, copied to host in global row order (float[n_views*n_channels]). */

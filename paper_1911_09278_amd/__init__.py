@@ -102,6 +102,10 @@ def _load():
     L.mace_visit_order.restype = ctypes.c_int
     L.mace_get_state.argtypes = [vp, vp, vp]
     L.mace_get_state.restype = ctypes.c_int
+    L.mace_get_slot_state.argtypes = [vp, i32, vp, vp]
+    L.mace_get_slot_state.restype = ctypes.c_int
+    L.mace_solve_volume.argtypes = [vp, i32, vp, vp, P(Prior), d, d, d, i32, i32, d, vp, P(Info)]
+    L.mace_solve_volume.restype = ctypes.c_int
     L.mace_get_error_sinogram.argtypes = [vp, vp]
     L.mace_get_error_sinogram.restype = ctypes.c_int
     L.mace_set_relaxation.argtypes = [vp, d]
@@ -153,7 +157,8 @@ EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_pnp", "mace_solve_dev"
             "mace_autotune", "mace_get_config",
             "mace_free_system", "mace_last_error", "mace_test_fail_alloc",
             "mace_solve_dev_noalloc", "mace_noalloc_capacity", "mace_set_fp32_tail",
-            "mace_solve_resume", "mace_server_cancel")
+            "mace_solve_resume", "mace_server_cancel", "mace_solve_volume",
+            "mace_get_slot_state")
 
 
 def noalloc_capacity() -> int:
@@ -311,6 +316,30 @@ class System:
                                     _ptr(ww), _ptr(XX), _ptr(x), ctypes.byref(info))
         _check(rc)
         return x, info
+
+    def solve_volume(self, y, lam, prior: Prior, b_axial, rho, sigma, max_iters, tol=0.0,
+                     sweeps=1):
+        """A volume of nz slices (C ABI mace_solve_volume): y, lam of shape
+        (nz, n_rows); returns (x of shape (nz, n), info)."""
+        yy = np.ascontiguousarray(y, dtype=np.float32)
+        ll = np.ascontiguousarray(lam, dtype=np.float32)
+        nz = yy.size // self.n_rows
+        if yy.size != nz * self.n_rows or ll.size != yy.size or nz < 1:
+            raise ValueError("y / lambda must hold nz whole sinograms")
+        x = np.empty((nz, self.n), dtype=np.float32)
+        info = Info()
+        rc = _lib.mace_solve_volume(self._h, nz, _ptr(yy), _ptr(ll), ctypes.byref(prior),
+                                    float(b_axial), float(rho), float(sigma), int(sweeps),
+                                    int(max_iters), float(tol), _ptr(x), ctypes.byref(info))
+        _check(rc)
+        return x, info
+
+    def slot_state(self, slot):
+        """(w, X) of scan slot `slot` (slice `slot` of a volume)."""
+        w = np.empty(self.N * self.n, dtype=np.float32)
+        X = np.empty(self.N * self.n, dtype=np.float32)
+        _check(_lib.mace_get_slot_state(self._h, int(slot), _ptr(w), _ptr(X)))
+        return w.reshape(self.N, self.n), X.reshape(self.N, self.n)
 
     def solve_pnp(self, y, lam, rho, sigma, max_iters, h_passes=1, tol=0.0, sweeps=1):
         """MACE with the stand-in PnP denoiser (C ABI mace_solve_pnp): host

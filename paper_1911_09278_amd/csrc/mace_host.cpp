@@ -574,7 +574,7 @@ struct HostSchedule {
 // placed in workgroups of XCD a mod 8, so the agent's sinogram blocks and its
 // matrix records stay in one L2; all slots walk the SVs in the same order, so
 // the same records are read by several slots at about the same time.
-static void build_schedule(const mace_system* s, int n_slots, int only_agent, int P,
+static void build_schedule(const mace_system* s, int n_slots, int only_agent, int P, int parity,
                            HostSchedule& hs) {
   std::vector<int> agents;
   if (only_agent >= 0)
@@ -589,9 +589,12 @@ static void build_schedule(const mace_system* s, int n_slots, int only_agent, in
   // rank-major: the rows that run at the same time (consecutive workgroups)
   // hold the same rank of every slot and agent, so the slots of a batch
   // walk the super-voxels in step and share the matrix records in L2
+  // (parity 0 / 1: only the even / odd slots -- the slices of a volume)
   for (int r = 0; r < P; ++r)
-    for (int sl = 0; sl < n_slots; ++sl)
+    for (int sl = 0; sl < n_slots; ++sl) {
+      if (parity >= 0 && (sl & 1) != parity) continue;
       for (size_t i = 0; i < agents.size(); ++i) xrows[agents[i] % nxcd].push_back({sl, agents[i], r});
+    }
   int wg_per_xcd = 0, used = 0;
   for (int x = 0; x < nxcd; ++x) {
     wg_per_xcd = std::max<int>(wg_per_xcd, (int)((xrows[x].size() + s->rpb - 1) / s->rpb));
@@ -632,9 +635,10 @@ static void build_schedule(const mace_system* s, int n_slots, int only_agent, in
   }
 }
 
-// Every (slot, agent, SV) of the scheduled agents appears exactly once per
-// pass, in the phase of its colour, and every task id is in range.
-static int check_schedule(const mace_system* s, int n_slots, int only_agent, const HostSchedule& hs) {
+// Every (slot, agent, SV) of the scheduled agents and slots appears exactly
+// once per pass, in the phase of its colour, and every task id is in range.
+static int check_schedule(const mace_system* s, int n_slots, int only_agent, int parity,
+                          const HostSchedule& hs) {
   const size_t per_slot = (size_t)s->N * s->n_sv;
   if (per_slot >= ((size_t)1 << kSlotShift)) return fail(MACE_E_ARG, "check: too many (agent, SV) pairs");
   if (n_slots > kMaxScanSlots) return fail(MACE_E_ARG, "check: too many slots");
@@ -651,7 +655,7 @@ static int check_schedule(const mace_system* s, int n_slots, int only_agent, con
   for (int sl = 0; sl < n_slots; ++sl)
     for (int a = 0; a < s->N; ++a)
       for (int sv = 0; sv < s->n_sv; ++sv) {
-        const int want = (only_agent < 0 || only_agent == a) ? 1 : 0;
+        const int want = (only_agent < 0 || only_agent == a) && (parity < 0 || (sl & 1) == parity) ? 1 : 0;
         const int got = seen[(size_t)sl * per_slot + (size_t)a * s->n_sv + sv];
         if (got != want) return fail(MACE_E_ARG, "check: task visited %d times", got);
       }
@@ -659,13 +663,13 @@ static int check_schedule(const mace_system* s, int n_slots, int only_agent, con
 }
 
 namespace mace {
-Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P) {
-  const auto key = std::make_tuple(n_slots, only_agent, P);
+Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P, int parity) {
+  const auto key = std::make_tuple(n_slots, only_agent, P, parity);
   auto it = s->schedules.find(key);
   if (it != s->schedules.end()) return it->second.get();
   HostSchedule hs;
-  build_schedule(s, n_slots, only_agent, P, hs);
-  if (check_schedule(s, n_slots, only_agent, hs)) return nullptr;
+  build_schedule(s, n_slots, only_agent, P, parity, hs);
+  if (check_schedule(s, n_slots, only_agent, parity, hs)) return nullptr;
   auto sch = std::make_unique<Schedule>();
   sch->grid = hs.grid;
   sch->R = hs.R;
@@ -901,12 +905,13 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
   const int P = default_rows_per_agent(&s);
   for (int only = -1; only < s.N; ++only) {
     for (int PP : {1, P}) {
-      for (int ns : {1, 3}) {
-        HostSchedule hs;
-        build_schedule(&s, ns, only, PP, hs);
-        rc = check_schedule(&s, ns, only, hs);
-        if (rc) return rc;
-      }
+      for (int ns : {1, 3})
+        for (int par : {-1, 0, 1}) {  // all slots; the even / odd slices of a volume
+          HostSchedule hs;
+          build_schedule(&s, ns, only, PP, par, hs);
+          rc = check_schedule(&s, ns, only, par, hs);
+          if (rc) return rc;
+        }
     }
     if (only >= 2) break;
   }

@@ -84,6 +84,8 @@ struct SvArgs {
   const float* gval;    // general records: values [N * n][nzp]
   const uint16_t* grow; // general records: LDS rows of the task's band [N * n][nzp]
   int nzp;              // general records: entries per (agent, pixel), a multiple of 16
+  int vol_nz;           // volume of vol_nz slices, slice z in slot z (0: independent scans)
+  float baxial;         // weight of the axial cliques of a volume
 };
 
 // Per-variant sweep launchers (mace_sweep_*.hip); general records for
@@ -103,8 +105,10 @@ int sv_rows_per_block(int bmax, int S, int kpad, int format);
 size_t sv_lds_bytes(int bmax, int S, int kpad, int format);
 // Doubles the epilogue needs after a slot's task partials.
 size_t epilogue_scratch_doubles();
+// The epilogue of each slot: consensus w-bar and the FP64 residual; with
+// `sums`, also each slot's (numerator, denominator, ||X||^2) at sums[slot * 4].
 hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int nparts,
-                           hipStream_t st);
+                           hipStream_t st, double* sums = nullptr);
 // MACE-PnP consensus G_H: `passes` applications of the 3x3 binomial smoother
 // to every active slot's wbar (through its aux buffer).
 hipError_t launch_smooth(const SlotDesc* slots, int n_slots, int nx, int ny, int passes,

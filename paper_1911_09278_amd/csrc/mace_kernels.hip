@@ -80,7 +80,7 @@ __device__ void block_sum3(double s0, double s1, double s2, double* out) {
 }
 
 __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restrict__ slots, int N,
-                                                       int n, int nparts) {
+                                                       int n, int nparts, double* sums) {
   const SlotDesc d = slots[blockIdx.y];
   if (!d.active) return;
   const int tid = threadIdx.x;
@@ -140,17 +140,23 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
     const double r = !finite ? __builtin_nan("") : den > 0.0 ? sqrt(bs[0]) / sqrt(den) : 0.0;
     if (k < d.resid_cap) d.resid[k] = r;
     *d.last = r;
+    if (sums) {  // the slot's sums, for statistics over several slots (volumes)
+      sums[blockIdx.y * 4 + 0] = bs[0];
+      sums[blockIdx.y * 4 + 1] = bs[1];
+      sums[blockIdx.y * 4 + 2] = bs[2];
+    }
     d.counter[0] = k + 1;
     d.counter[1] = 0;
   }
 }
 
 hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int nparts,
-                           hipStream_t st) {
+                           hipStream_t st, double* sums) {
   if (n_slots <= 0) return hipSuccess;
   int gx = (n + 255) / 256;
   if (gx > kEpiBlocks) gx = kEpiBlocks;
-  hipLaunchKernelGGL(epilogue_kernel, dim3(gx, n_slots), dim3(256), 0, st, slots, N, n, nparts);
+  hipLaunchKernelGGL(epilogue_kernel, dim3(gx, n_slots), dim3(256), 0, st, slots, N, n, nparts,
+                     sums);
   return hipGetLastError();
 }
 

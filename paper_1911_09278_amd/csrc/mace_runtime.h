@@ -120,6 +120,7 @@ struct Batch {
   DevBuf<SlotDesc> table;  // device slot table, kMaxScanSlots entries
   std::vector<SlotDesc> htable;
   DevBuf<double> lastres;  // latest residual of each slot
+  DevBuf<double> sums;     // volumes: each slot's residual sums, [kMaxScanSlots][4]
   std::map<std::tuple<int, int, int, int, uint64_t>, std::unique_ptr<IterGraph>> graphs;
 };
 
@@ -154,7 +155,7 @@ struct mace_system {
   mace::DevBuf<int> band_rows;
   mace::DevBuf<int> d_sv_pix0;
   mace::DevBuf<int> row_src;  // agent-block row -> global row (or -1)
-  std::map<std::tuple<int, int, int>, std::unique_ptr<mace::Schedule>> schedules;
+  std::map<std::tuple<int, int, int, int>, std::unique_ptr<mace::Schedule>> schedules;
   // slot 0 serves mace_solve / mace_prox; mace_solve_batch uses 0..B-1
   mace::Batch batch;
   hipStream_t stream = nullptr;
@@ -168,7 +169,8 @@ struct mace_system {
 
 namespace mace {
 int default_rows_per_agent(const mace_system* s);
-Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P);
+// Task tables for n_slots slots (parity 0 / 1: only the even / odd slots).
+Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P, int parity = -1);
 int check_prior(const mace_prior* pr);
 void fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, double rho, double sigma,
                bool fp16);

@@ -67,6 +67,7 @@ int ensure_slot(mace_system* s, Batch& b, int idx, int resid_cap) {
   }
   // allocated once at the maximum size: captured graphs hold these addresses
   if (b.lastres.count < (size_t)kMaxScanSlots) HIP_OK(b.lastres.alloc(kMaxScanSlots));
+  if (b.sums.count < (size_t)kMaxScanSlots * 4) HIP_OK(b.sums.alloc((size_t)kMaxScanSlots * 4));
   if (b.table.count < (size_t)kMaxScanSlots) {
     HIP_OK(b.table.alloc(kMaxScanSlots));
     b.htable.assign(kMaxScanSlots, SlotDesc{});
@@ -469,7 +470,145 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
   return worst;
 }
 
+// A volume (nz slices measured by this system's 2-D matrix, coupled by the
+// axial cliques of the 3-D prior): slice z runs in slot z.  Each colour
+// phase is two launches, the even slices and then the odd ones, so a slice's
+// axial neighbours hold still while it sweeps and both see the other
+// parity's latest values (a red-black order over the slices).  The Mann
+// iteration, the consensus and the residual are those of the stacked volume
+// (Algorithm 1 over all nz * n voxels): the slices stop together, when
+// r_k = ||X^{k+1} - G w^k|| / ||w^k|| over the whole volume is below tol.
+// y, lam: device, nz blocks of the global row order; x_out: device, nz * n.
+int solve_volume_impl(mace_system* s, int nz, const float* y, const float* lam,
+                      const mace_prior* pr, double b_axial, double rho, double sigma, int sweeps,
+                      int max_iters, double tol, float* x_out, mace_info* info) {
+  int rc = check_prior(pr);
+  if (rc) return rc;
+  if (s->format != 1)
+    return fail(MACE_E_ARG, "volumes need the general record format (load the system with format 2)");
+  if (nz < 1 || nz > kMaxScanSlots) return fail(MACE_E_ARG, "nz must be in [1, %d]", kMaxScanSlots);
+  if (!(b_axial >= 0) || !std::isfinite(b_axial)) return fail(MACE_E_ARG, "b_axial must be >= 0");
+  if (!(rho > 0 && rho < 1)) return fail(MACE_E_ARG, "rho must be in (0, 1)");
+  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(MACE_E_ARG, "sigma must be > 0");
+  if (sweeps < 1) return fail(MACE_E_ARG, "sweeps must be >= 1");
+  if (max_iters < 0) return fail(MACE_E_ARG, "max_iters must be >= 0");
+  Batch& b = s->batch;
+  hipStream_t st = s->stream;
+  // rows per agent for the slices of one parity together
+  const int P = batch_rows_per_agent(s, (nz + 1) / 2, false);
+  const Schedule* sch[2] = {get_schedule(s, nz, -1, P, 0),
+                            nz > 1 ? get_schedule(s, nz, -1, P, 1) : nullptr};
+  if (!sch[0] || (nz > 1 && !sch[1])) return fail(MACE_E_HIP, "schedule upload failed");
+  for (int z = 0; z < nz; ++z) {
+    rc = ensure_slot(s, b, z, max_iters);
+    if (rc) return rc;
+  }
+  SvArgs a;
+  fill_args(s, a, pr, rho, sigma, false);
+  a.strict = P == 1 ? 1 : 0;
+  a.vol_nz = nz;
+  a.baxial = (float)b_axial;
+  const size_t m = (size_t)s->n_views * s->n_ch;
+  for (int z = 0; z < nz; ++z) {
+    rc = start_slot(s, b, z, y + z * m, lam + z * m, nullptr, a, st, nullptr);
+    if (rc) return rc;
+  }
+  for (int i = nz; i < (int)b.htable.size(); ++i)
+    if (b.htable[i].active) {
+      rc = write_slot(s, b, i, 0, st);
+      if (rc) return rc;
+    }
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad, s->format);
+  a.slots = b.table.p;
+  std::vector<double> sums((size_t)nz * 4);
+  double r = 0.0;
+  int it = 0, status = MACE_OK;
+  auto residual = [&]() -> int {
+    HIP_OK(hipMemcpyAsync(sums.data(), b.sums.p, sizeof(double) * 4 * nz, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    double num = 0.0, den = 0.0, xx = 0.0;
+    for (int z = 0; z < nz; ++z) {  // slice order: a fixed summation order
+      num += sums[z * 4 + 0];
+      den += sums[z * 4 + 1];
+      xx += sums[z * 4 + 2];
+    }
+    const double d = den > 0.0 ? den : xx;
+    r = !(std::isfinite(num) && std::isfinite(den) && std::isfinite(xx)) ? std::nan("")
+        : d > 0.0 ? std::sqrt(num) / std::sqrt(d) : 0.0;
+    return MACE_OK;
+  };
+  for (; it < max_iters; ++it) {
+    for (int sw = 0; sw < sweeps; ++sw) {
+      a.mann = (sw == sweeps - 1) ? 1 : 0;
+      for (int c = 0; c < 4; ++c)
+        for (int par = 0; par < 2; ++par) {
+          if (!sch[par]) continue;
+          a.R = sch[par]->R;
+          a.tasks = sch[par]->tasks[c].p;
+          a.T = sch[par]->T[c];
+          HIP_OK(launch_sv(a, kSweep, s->slots, sch[par]->grid, lds, st));
+        }
+    }
+    HIP_OK(launch_epilogue(b.table.p, nz, s->N, s->n, s->N * s->n_sv, st, b.sums.p));
+    if (tol > 0) {
+      rc = residual();
+      if (rc) return rc;
+      if (!std::isfinite(r)) {
+        status = MACE_E_NONFINITE;
+        ++it;
+        break;
+      }
+      if (r < tol) {
+        ++it;
+        break;
+      }
+    }
+  }
+  if (it > 0 && tol <= 0) {
+    rc = residual();
+    if (rc) return rc;
+    if (!std::isfinite(r)) status = MACE_E_NONFINITE;
+  }
+  for (int z = 0; z < nz; ++z) {
+    ScanSlot& q = *b.scan[z];
+    if (it == 0) HIP_OK(launch_broadcast_mean(q.w.p, q.wbar.p, q.X.p, s->N, s->n, st));
+    HIP_OK(hipMemcpyAsync(x_out + (size_t)z * s->n, q.wbar.p, sizeof(float) * s->n,
+                          hipMemcpyDeviceToDevice, st));
+  }
+  HIP_OK(hipStreamSynchronize(st));
+  if (status == MACE_OK && tol > 0 && !(r < tol)) status = MACE_W_MAXITER;
+  if (info) {
+    *info = mace_info{};
+    info->iters = it;
+    info->residual = r;
+    info->equits = (double)sweeps * it;
+    info->status = status;
+  }
+  if (status == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "non-finite residual");
+  return status;
+}
+
 }  // namespace
+
+extern "C" int mace_solve_volume(mace_system* s, int32_t nz, const float* y, const float* lam,
+                                 const mace_prior* pr, double b_axial, double rho, double sigma,
+                                 int32_t sweeps, int32_t max_iters, double tol, float* x_out,
+                                 mace_info* info) {
+  if (!s || !y || !lam || !x_out) return fail(MACE_E_ARG, "NULL argument");
+  if (nz < 1 || nz > kMaxScanSlots) return fail(MACE_E_ARG, "nz must be in [1, %d]", kMaxScanSlots);
+  const size_t m = (size_t)s->n_views * s->n_ch;
+  DevBuf<float> dy, dl, dx;
+  HIP_OK(dy.upload(y, m * nz));
+  HIP_OK(dl.upload(lam, m * nz));
+  HIP_OK(dx.alloc((size_t)s->n * nz));
+  int rc = solve_volume_impl(s, nz, dy.p, dl.p, pr, b_axial, rho, sigma, sweeps, max_iters, tol,
+                             dx.p, info);
+  if (rc < 0 && rc != MACE_E_NONFINITE) return rc;
+  const std::string saved = last_error_text();
+  HIP_OK(hipMemcpy(x_out, dx.p, sizeof(float) * s->n * nz, hipMemcpyDeviceToHost));
+  if (rc == MACE_E_NONFINITE) return fail(MACE_E_NONFINITE, "%s", saved.c_str());
+  return rc;
+}
 
 extern "C" int mace_solve_dev(mace_system* s, const float* y, const float* lam,
                               const mace_prior* pr, double rho, double sigma, int32_t sweeps,
@@ -643,6 +782,16 @@ extern "C" int mace_get_state(const mace_system* s, float* w, float* X) {
   const size_t bytes = (size_t)s->N * s->n * sizeof(float);
   if (w) HIP_OK(hipMemcpy(w, s->batch.scan[0]->w.p, bytes, hipMemcpyDeviceToHost));
   if (X) HIP_OK(hipMemcpy(X, s->batch.scan[0]->X.p, bytes, hipMemcpyDeviceToHost));
+  return MACE_OK;
+}
+
+extern "C" int mace_get_slot_state(const mace_system* s, int32_t slot, float* w, float* X) {
+  if (!s) return fail(MACE_E_ARG, "NULL system");
+  if (slot < 0 || slot >= (int)s->batch.scan.size() || !s->batch.scan[slot]->w.p)
+    return fail(MACE_E_ARG, "slot %d holds no state", slot);
+  const size_t bytes = (size_t)s->N * s->n * sizeof(float);
+  if (w) HIP_OK(hipMemcpy(w, s->batch.scan[slot]->w.p, bytes, hipMemcpyDeviceToHost));
+  if (X) HIP_OK(hipMemcpy(X, s->batch.scan[slot]->X.p, bytes, hipMemcpyDeviceToHost));
   return MACE_OK;
 }
 

@@ -14,7 +14,12 @@
 //     number of views: the band is staged and written back view by view in
 //     chunks of 16 channels;
 //   * the staged copy of e that the write-back subtracts lives in LDS;
-//   * super-voxel sides 4, 8, 16 and 32.
+//   * super-voxel sides 4, 8, 16 and 32;
+//   * volumes: slice z of a stack lives in slot z, and lanes 9 and 10 add
+//     the axial cliques to the voxels of slices z - 1 and z + 1 of the same
+//     agent (the 3-D prior's ten-voxel neighbourhood).  Even and odd slices
+//     sweep in separate launches, so the axial neighbours a task stages do
+//     not change while it runs.
 // Loops over records, views and pixels are not unrolled.  FP32 values only.
 #include <hip/hip_runtime.h>
 
@@ -24,9 +29,10 @@
 namespace mace {
 
 // LDS bytes of one row of the general kernel: band (e, Lambda), the staged
-// e, the halo tile and v / theta2 of the super-voxel's pixels.
+// e, the halo tile, and v / theta2 / the axial neighbours below and above of
+// the super-voxel's pixels.
 __host__ __device__ inline size_t gen_row_lds_bytes(int bmax, int S) {
-  size_t per_row = (size_t)bmax * 12 + (size_t)halo_cells(S) * 4 + (size_t)S * S * 8;
+  size_t per_row = (size_t)bmax * 12 + (size_t)halo_cells(S) * 4 + (size_t)S * S * 16;
   per_row = (per_row + 7) & ~(size_t)7;
   const size_t red = kRowLanes * 3 * sizeof(double);
   return per_row > red ? per_row : red;
@@ -48,10 +54,15 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
   float* halo = e0l + a.bmax;
   float* vv = halo + NHC;
   float* t2 = vv + S * S;
+  float* xlo = t2 + S * S;  // volumes: the agent's voxels in slices z - 1, z + 1
+  float* xhi = xlo + S * S;
 
   const int ndi = (lr < 3) ? -1 : (lr < 5 ? 0 : 1);
   const int ndj = (lr == 0 || lr == 3 || lr == 5) ? -1 : ((lr == 1 || lr == 6) ? 0 : 1);
-  const float nbw = lr < 8 ? ((ndi != 0 && ndj != 0) ? a.bdiag : a.bedge) * a.invN : 0.0f;
+  // lanes 9 and 10: the axial neighbours below and above (volumes)
+  const bool axial = a.vol_nz > 0 && (lr == 9 || lr == 10);
+  const float nbw = lr < 8 ? ((ndi != 0 && ndj != 0) ? a.bdiag : a.bedge) * a.invN
+                           : (axial ? a.baxial * a.invN : 0.0f);
   const int noff = lr < 8 ? ndi * HS + ndj : 0;
   const int ndi8 = lr < 8 ? ndi : 0, ndj8 = lr < 8 ? ndj : 0;
   const float proxw = lr == 8 ? a.is2 : 0.0f;
@@ -81,6 +92,8 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
     gptr<double> cpart = glb(sd->part);
     const BandEnt* be = a.band + asv * a.kpad;
     const int B = a.band_rows[asv];
+    const int z = raw >> kSlotShift;  // volumes: the task's slice
+    const bool has_lo = a.vol_nz > 0 && z > 0, has_hi = a.vol_nz > 0 && z + 1 < a.vol_nz;
 
     // ---- 1. stage the band view by view, 16 channels at a time ----
     for (int k = 0; k < a.kpad; ++k) {
@@ -109,6 +122,16 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
         vv[p] = 2.0f * cwbar[pix] - cw[img + pix];
         t2[p] = cth2[img + pix];
       }
+      if (a.vol_nz > 0) {
+        gptr<const float> Xlo = glb((const float*)a.slots[has_lo ? z - 1 : z].X);
+        gptr<const float> Xhi = glb((const float*)a.slots[has_hi ? z + 1 : z].X);
+        for (int p = lr; p < npix; p += kRowLanes) {
+          const int pi = p / sw, pj = p - (p / sw) * sw;
+          const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
+          xlo[p] = has_lo ? Xlo[img + pix] : 0.0f;
+          xhi[p] = has_hi ? Xhi[img + pix] : 0.0f;
+        }
+      }
     }
     __builtin_amdgcn_wave_barrier();
 
@@ -126,10 +149,14 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
           part += gv[q] * p.y * p.x;
         }
         const float zs = halo[cidx];
-        const float nbv = halo[cidx + noff];
+        float nbv = halo[cidx + noff];
         const float vj = vv[j], tj = t2[j];
         const int iy = y0 + pi + ndi8, ix = x0 + pj + ndj8;
-        const float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+        float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+        if (axial) {
+          nbv = lr == 9 ? xlo[j] : xhi[j];
+          nin = (lr == 9 ? has_lo : has_hi) ? 1.0f : 0.0f;
+        }
         const float d = zs - nbv;
         const float wgt = nbw * nin * prior_curv(a, d);
         const float gl = wgt * d + proxw * (zs - vj) - part;

@@ -1,0 +1,138 @@
+"""GPU parity of volume reconstruction (slice stacks with axial cliques)
+against the oracle's 3-D problem.
+
+A volume is nz slices measured by one 2-D matrix; the prior adds the axial
+cliques (z, s)-(z + 1, s) with weight b_axial to every slice's 8 in-plane
+cliques, and partial-update MACE runs over the stacked voxels.  The GPU
+sweeps each colour phase twice, the even slices and then the odd ones.
+
+1. Sequential schedule (one row per agent): the trajectory equals the
+   oracle's, run in the GPU's visiting order (colour c, then the even
+   slices, then the odd slices; super-voxels and raster order inside), with
+   the same coordinate rule -- every slice's X_i and x, element by element
+   (5e-5 of max|x|, the FP32 budget of the 2-D parity tests), and the stacked
+   residual.
+2. Concurrent schedule: the fixed point equals the volume's MAP image (the
+   oracle's conjugate-gradient solve of the 3-D normal equations, pinned to
+   the dense 3-D MAP in the oracle tests) to NRMSE 1e-4.
+3. b_axial = 0: every slice of the volume equals the same slice solved alone
+   (the sequential schedule, same visiting order inside a slice).
+4. Argument errors.
+"""
+import numpy as np
+import pytest
+
+import mace_inputs as mi
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1911_09278_amd as lib
+    return lib
+
+
+def _volume(g, nz, seed, N, kind, sx, ba, q=2.0):
+    cp, row, val = mi.system_matrix(g)
+    scans = [mi.scan(g, seed + z) for z in range(nz)]
+    y = np.stack([s.y for s in scans])
+    lam = np.stack([s.lam for s in scans])
+    va = mi.interleaved_partition(g.n_views, N)
+    O = oracle.Oracle(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, y.reshape(-1),
+                      lam.reshape(-1), va, kind, sx, 2.0, q, 1.0, nz=nz, b_axial=ba)
+    return (cp, row, val), y, lam, O
+
+
+def _volume_order(sysm, g, nz, S):
+    """The GPU's sequential visiting order over the voxels v = z n + s."""
+    o2 = sysm.visit_order()
+    col = ((o2 % g.nx) // S & 1) + 2 * ((o2 // g.nx) // S & 1)
+    out = []
+    for c in range(4):
+        part = o2[col == c]
+        for par in (0, 1):
+            for z in range(par, nz, 2):
+                out.append(z * g.n + part)
+    return np.concatenate(out)
+
+
+SEQ_CASES = [
+    # geometry, nz, N, prior kind, sigma_x, q, b_axial, sigma, S, iterations
+    (mi.Geometry(24, 24, 24, 36), 3, 2, 1, 0.002, 1.2, 0.5, 0.001, 8, 4),
+    (mi.Geometry(20, 18, 30, 30), 4, 3, 0, 0.003, 2.0, 0.25, 0.002, 4, 3),
+    (mi.Geometry(16, 16, 16, 24), 2, 2, 1, 0.002, 1.2, 1.0, 0.001, 4, 3),
+]
+
+
+@pytest.mark.parametrize("case", SEQ_CASES,
+                         ids=lambda c: f"{c[0].nx}x{c[0].ny}z{c[1]}_N{c[2]}_k{c[3]}_ba{c[6]}")
+def test_volume_sequential_trajectory_matches_oracle(m, case):
+    g, nz, N, kind, sx, q, ba, sigma, S, iters = case
+    (cp, row, val), y, lam, O = _volume(g, nz, 301 + g.nx, N, kind, sx, ba, q)
+    print(f"case {g} nz={nz} N={N} b_axial={ba}", flush=True)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=S,
+                    rows_per_agent=1, format=2)
+    prior = m.make_prior(kind, sx, 2.0, q, 1.0)
+    x, info = sysm.solve_volume(y, lam, prior, ba, 0.8, sigma, iters)
+    order = _volume_order(sysm, g, nz, S)
+    assert np.array_equal(np.sort(order), np.arange(nz * g.n))
+    ref = O.mace_solve(0.8, sigma, iters, order=order, mode=oracle.MODE_SURROGATE)
+    scale = np.abs(ref["x"]).max()
+    assert np.all(np.isfinite(x))
+    assert np.abs(x.reshape(-1) - ref["x"]).max() <= 5e-5 * scale
+    for z in range(nz):
+        _, Xz = sysm.slot_state(z)
+        err = np.abs(Xz - ref["X"][:, z * g.n:(z + 1) * g.n]).max()
+        assert err <= 5e-5 * scale, (z, err / scale)
+    assert info.iters == iters
+    assert abs(info.residual - ref["resid"][-1]) <= 1e-3 * ref["resid"][-1] + 1e-7
+
+
+def test_volume_concurrent_fixed_point_is_the_map(m):
+    g = mi.Geometry(64, 64, 48, 96)
+    nz, N, sx, ba, sigma = 4, 4, 0.001, 0.5, 5e-4
+    (cp, row, val), y, lam, O = _volume(g, nz, 17, N, 0, sx, ba)
+    xmap, _, rel = O.map_cg(rtol=1e-13)
+    assert rel <= 1e-12
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, format=2)
+    assert sysm.config["rows_per_agent"] > 1
+    sysm.set_relaxation(0.5)
+    x, info = sysm.solve_volume(y, lam, m.make_prior(0, sx), ba, 0.8, sigma, 20000, tol=1e-8)
+    e = float(np.linalg.norm(x.reshape(-1).astype(np.float64) - xmap) / np.linalg.norm(xmap))
+    print(f"volume {g} nz={nz}: {info.iters} iterations, r {info.residual:.2e}, nrmse {e:.2e}",
+          flush=True)
+    assert info.status == m.MACE_OK
+    assert e <= 1e-4
+
+
+def test_volume_without_axial_cliques_is_independent_slices(m):
+    g = mi.Geometry(24, 24, 24, 36)
+    nz, N, sx, sigma = 3, 2, 0.002, 0.001
+    (cp, row, val), y, lam, _ = _volume(g, nz, 41, N, 1, sx, 0.0, 1.2)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=8,
+                    rows_per_agent=1, format=2)
+    prior = m.make_prior(1, sx, 2.0, 1.2, 1.0)
+    xv, _ = sysm.solve_volume(y, lam, prior, 0.0, 0.8, sigma, 5)
+    for z in range(nz):
+        xs, _ = sysm.solve(y[z], lam[z], prior, 0.8, sigma, 5)
+        assert np.abs(xv[z] - xs).max() <= 1e-6 * np.abs(xs).max()
+
+
+def test_volume_argument_errors(m):
+    g = mi.Geometry(24, 24, 24, 36)
+    (cp, row, val), y, lam, _ = _volume(g, 2, 5, 2, 0, 0.002, 0.5)
+    prior = m.make_prior(0, 0.002)
+    compact = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, format=1)
+    with pytest.raises(m.MaceError) as ei:
+        compact.solve_volume(y, lam, prior, 0.5, 0.8, 0.001, 2)
+    assert ei.value.code == m.MACE_E_ARG and "general record format" in str(ei.value)
+    general = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, format=2)
+    with pytest.raises(m.MaceError) as ei:
+        general.solve_volume(y, lam, prior, -1.0, 0.8, 0.001, 2)
+    assert ei.value.code == m.MACE_E_ARG
+    with pytest.raises(ValueError):
+        general.solve_volume(y[:, :-1], lam[:, :-1], prior, 0.5, 0.8, 0.001, 2)
