@@ -101,7 +101,9 @@ def test_volume_concurrent_fixed_point_is_the_map(m):
     sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, format=2)
     assert sysm.config["rows_per_agent"] > 1
     sysm.set_relaxation(0.5)
-    x, info = sysm.solve_volume(y, lam, m.make_prior(0, sx), ba, 0.8, sigma, 20000, tol=1e-8)
+    # r < 1e-7: the concurrent schedule's FP32 iterates level off near
+    # r = 1e-8, and 1e-7 already leaves NRMSE ~2e-5 to the MAP
+    x, info = sysm.solve_volume(y, lam, m.make_prior(0, sx), ba, 0.8, sigma, 20000, tol=1e-7)
     e = float(np.linalg.norm(x.reshape(-1).astype(np.float64) - xmap) / np.linalg.norm(xmap))
     print(f"volume {g} nz={nz}: {info.iters} iterations, r {info.residual:.2e}, nrmse {e:.2e}",
           flush=True)
