@@ -327,6 +327,30 @@ def test_configured_sigma_diverges_on_64x64():
     assert np.abs(np.linalg.eigvals(M)).max() > 1.0
 
 
+def test_P5_partial_updates_lose_stability_in_a_band_of_sigma():
+    """Theorem 2 covers small sigma only.  The exact linear map of partial-
+    update MACE (12x12, 24 views, 4 agents, rho = 0.8) has spectral radius
+    below 1 at small sigma; with a weak prior (sigma_x = 0.02) it exceeds 1
+    in a middle band of sigma (sigma^2 theta2 from about 1 to about 400),
+    and with a prior ten times stronger (sigma_x = 0.002) it stays below 1
+    at every sigma, smallest near sigma^2 theta2 = 1."""
+    gs = mi.Geometry(12, 12, 24, 18)
+
+    def radius(sx, sigma):
+        O2, A2, lam2, y2, va2 = _problem(gs, 5, 4, 0, sx)
+        Hs, bs = dr.agent_system(gs, A2, lam2, y2, dr.laplacian(12, 12), sx, va2, 4)
+        M, _ = dr.pu_mace_linear_map(Hs, bs, sigma, 0.8)
+        return float(np.abs(np.linalg.eigvals(M)).max())
+
+    assert radius(0.02, 1e-3) < 1.0
+    assert radius(0.02, 3e-3) > 1.0
+    assert radius(0.02, 1e-2) > 1.15
+    assert radius(0.02, 1e-1) > 1.0
+    strong = [radius(0.002, sg) for sg in (1e-3, 3e-3, 1e-2, 3e-2, 1e-1)]
+    assert max(strong) < 1.0
+    assert min(strong) == strong[1] and strong[1] < 0.8
+
+
 # ---------------- P6 ----------------
 def test_P6_single_agent_reaches_centralised_map():
     g = mi.Geometry(16, 16, 32, 24)
