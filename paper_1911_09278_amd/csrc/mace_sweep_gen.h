@@ -20,7 +20,10 @@
 //     agent (the 3-D prior's ten-voxel neighbourhood).  Even and odd slices
 //     sweep in separate launches, so the axial neighbours a task stages do
 //     not change while it runs.
-// Loops over records, views and pixels are not unrolled.  FP32 values only.
+// Records of up to 256 entries (the common case: 1 mm channels and tens of
+// views per agent) are held in registers in the sweep, loaded two pixels
+// ahead; longer ones are read in the pixel loop.  Loops over views and
+// pixels are not unrolled.  FP32 values only.
 #include <hip/hip_runtime.h>
 
 #include "mace_internal.h"
@@ -38,7 +41,33 @@ __host__ __device__ inline size_t gen_row_lds_bytes(int bmax, int S) {
   return per_row > red ? per_row : red;
 }
 
-template <int MODE, int S>
+// The lane's share of a general record: entries lr, lr + 16, ... of the
+// pixel's list, nzp / 16 <= NZL of them (the list's own padding holds 0 on
+// the task's dummy row).
+template <int NZL>
+struct GenRec {
+  float val[NZL];
+  int row[NZL];
+};
+
+template <int NZL>
+__device__ __forceinline__ void load_gen(const SvArgs& a, size_t rec0, int j, int lr,
+                                         GenRec<NZL>& g) {
+  const float* gv = a.gval + (rec0 + j) * (size_t)a.nzp + lr;
+  const uint16_t* gr = a.grow + (rec0 + j) * (size_t)a.nzp + lr;
+  const int nu = a.nzp / kRowLanes;  // the same for every lane: nzp is a multiple of 16
+#pragma unroll
+  for (int u = 0; u < NZL; ++u)
+    if (u < nu) {  // slots past nu are never read
+      g.val[u] = gv[u * kRowLanes];
+      g.row[u] = gr[u * kRowLanes];
+    }
+}
+
+// NZL > 0 (sweep mode only): records of at most 16 NZL entries, held in
+// registers and loaded two pixels ahead; NZL = 0: any length, read in the
+// pixel loop.
+template <int MODE, int S, int NZL>
 __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
   constexpr int HS = S + 2;
   constexpr int NHC = halo_cells(S);
@@ -137,49 +166,90 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
 
     // ---- 2. pixel loop ----
     const size_t rec0 = (size_t)agent * a.n + (size_t)a.sv_pix0[sv];
-    for (int j = 0; j < npix; ++j) {
+    // The coordinate step of pixel j (sweep mode) from the lane's share of
+    // theta1's sum: alpha, with z_s updated in the halo.  The caller gathers
+    // `part` and applies alpha to the band.
+    auto step_alpha = [&](int j, float part) {
       const int pi = j / sw, pj = j - (j / sw) * sw;
       const int cidx = (pi + 1) * HS + pj + 1;
-      const float* gv = a.gval + (rec0 + j) * (size_t)a.nzp;
-      const uint16_t* gr = a.grow + (rec0 + j) * (size_t)a.nzp;
-      if (MODE == kSweep) {
-        float part = 0.0f;
-        for (int q = lr; q < a.nzp; q += kRowLanes) {
-          const float2 p = band[gr[q]];
-          part += gv[q] * p.y * p.x;
-        }
-        const float zs = halo[cidx];
-        float nbv = halo[cidx + noff];
-        const float vj = vv[j], tj = t2[j];
-        const int iy = y0 + pi + ndi8, ix = x0 + pj + ndj8;
-        float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
-        if (axial) {
-          nbv = lr == 9 ? xlo[j] : xhi[j];
-          nin = (lr == 9 ? has_lo : has_hi) ? 1.0f : 0.0f;
-        }
-        const float d = zs - nbv;
-        const float wgt = nbw * nin * prior_curv(a, d);
-        const float gl = wgt * d + proxw * (zs - vj) - part;
-        const float G = row_sum16(gl);
-        const float H = row_sum16(wgt);
-        const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(tj + H + a.is2);
-        // the rows of one column are distinct; padding entries add 0 to
-        // the dummy row
-        for (int q = lr; q < a.nzp; q += kRowLanes) band[gr[q]].x -= gv[q] * alpha;
-        if (lr == 0) halo[cidx] = zs + alpha;
-      } else if (MODE == kTheta2) {
-        float part = 0.0f;
-        for (int q = lr; q < a.nzp; q += kRowLanes) {
-          const float av = gv[q];
-          part += av * av * band[gr[q]].y;
-        }
-        const float th = row_sum16(part);
-        if (lr == 0) cth2[img + (size_t)(y0 + pi) * a.nx + x0 + pj] = th;
-      } else {
-        const float xs = halo[cidx];
-        for (int q = lr; q < a.nzp; q += kRowLanes) band[gr[q]].x -= gv[q] * xs;
+      const float zs = halo[cidx];
+      float nbv = halo[cidx + noff];
+      const float vj = vv[j], tj = t2[j];
+      const int iy = y0 + pi + ndi8, ix = x0 + pj + ndj8;
+      float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+      if (axial) {
+        nbv = lr == 9 ? xlo[j] : xhi[j];
+        nin = (lr == 9 ? has_lo : has_hi) ? 1.0f : 0.0f;
       }
-      __builtin_amdgcn_wave_barrier();
+      const float d = zs - nbv;
+      const float wgt = nbw * nin * prior_curv(a, d);
+      const float gl = wgt * d + proxw * (zs - vj) - part;
+      const float G = row_sum16(gl);
+      const float H = row_sum16(wgt);
+      const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(tj + H + a.is2);
+      if (lr == 0) halo[cidx] = zs + alpha;
+      return alpha;
+    };
+    // entries per lane: nzp is a multiple of 16, the same for every lane
+    const int nu = a.nzp / kRowLanes;
+    if constexpr (MODE == kSweep && NZL > 0) {
+      // records of at most 16 NZL entries: the lane's share in registers,
+      // loaded two pixels ahead
+      GenRec<NZL> buf[3];
+      load_gen<NZL>(a, rec0, 0, lr, buf[0]);
+      if (npix > 1) load_gen<NZL>(a, rec0, 1, lr, buf[1]);
+      for (int jb = 0; jb < npix; jb += 3) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int j = jb + q;
+          if (j < npix) {
+            if (j + 2 < npix) load_gen<NZL>(a, rec0, j + 2, lr, buf[(q + 2) % 3]);
+            const GenRec<NZL>& r = buf[q];
+            float part = 0.0f;
+#pragma unroll
+            for (int u = 0; u < NZL; ++u)
+              if (u < nu) {
+                const float2 p = band[r.row[u]];
+                part += r.val[u] * p.y * p.x;
+              }
+            const float alpha = step_alpha(j, part);
+            // the rows of one column are distinct; padding entries add 0 to
+            // the dummy row
+#pragma unroll
+            for (int u = 0; u < NZL; ++u)
+              if (u < nu) band[r.row[u]].x -= r.val[u] * alpha;
+            __builtin_amdgcn_wave_barrier();
+          }
+        }
+      }
+    } else {
+      for (int j = 0; j < npix; ++j) {
+        const int pi = j / sw, pj = j - (j / sw) * sw;
+        const int cidx = (pi + 1) * HS + pj + 1;
+        const float* gv = a.gval + (rec0 + j) * (size_t)a.nzp + lr;
+        const uint16_t* gr = a.grow + (rec0 + j) * (size_t)a.nzp + lr;
+        if (MODE == kSweep) {
+          float part = 0.0f;
+          for (int u = 0; u < nu; ++u) {
+            const float2 p = band[gr[u * kRowLanes]];
+            part += gv[u * kRowLanes] * p.y * p.x;
+          }
+          const float alpha = step_alpha(j, part);
+          for (int u = 0; u < nu; ++u) band[gr[u * kRowLanes]].x -= gv[u * kRowLanes] * alpha;
+        } else if (MODE == kTheta2) {
+          float part = 0.0f;
+          for (int u = 0; u < nu; ++u) {
+            const float av = gv[u * kRowLanes];
+            part += av * av * band[gr[u * kRowLanes]].y;
+          }
+          const float th = row_sum16(part);
+          if (lr == 0) cth2[img + (size_t)(y0 + pi) * a.nx + x0 + pj] = th;
+        } else {
+          const float xs = halo[cidx];
+          for (int u = 0; u < nu; ++u) band[gr[u * kRowLanes]].x -= gv[u * kRowLanes] * xs;
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
     }
 
     // ---- 3. write back, view by view ----
@@ -236,25 +306,30 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
   }
 }
 
-template <int MODE, int SV>
+template <int MODE, int SV, int NZL>
 inline hipError_t launch_gen_mode(const SvArgs& a, int grid, size_t lds, hipStream_t st) {
   static std::atomic<bool> attr_set{false};
   if (!attr_set.load(std::memory_order_acquire)) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel_gen<MODE, SV>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel_gen<MODE, SV, NZL>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kMaxLdsBytes);
     if (e != hipSuccess) return e;
     attr_set.store(true, std::memory_order_release);
   }
-  hipLaunchKernelGGL((sv_kernel_gen<MODE, SV>), dim3(grid), dim3(a.rpb * kRowLanes), lds, st, a);
+  hipLaunchKernelGGL((sv_kernel_gen<MODE, SV, NZL>), dim3(grid), dim3(a.rpb * kRowLanes), lds, st,
+                     a);
   return hipGetLastError();
 }
 
 template <int SV>
 inline hipError_t launch_gen_s(const SvArgs& a, int mode, int grid, size_t lds, hipStream_t st) {
-  if (mode == kSweep) return launch_gen_mode<kSweep, SV>(a, grid, lds, st);
-  if (mode == kTheta2) return launch_gen_mode<kTheta2, SV>(a, grid, lds, st);
-  return launch_gen_mode<kRefresh, SV>(a, grid, lds, st);
+  if (mode == kSweep) {
+    if (a.nzp <= 8 * kRowLanes) return launch_gen_mode<kSweep, SV, 8>(a, grid, lds, st);
+    if (a.nzp <= 16 * kRowLanes) return launch_gen_mode<kSweep, SV, 16>(a, grid, lds, st);
+    return launch_gen_mode<kSweep, SV, 0>(a, grid, lds, st);
+  }
+  if (mode == kTheta2) return launch_gen_mode<kTheta2, SV, 0>(a, grid, lds, st);
+  return launch_gen_mode<kRefresh, SV, 0>(a, grid, lds, st);
 }
 
 }  // namespace mace

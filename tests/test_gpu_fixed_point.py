@@ -53,14 +53,14 @@ def _nrmse(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
 
 
-def _solve(m, mats, s, prior, **opts):
+def _solve(m, mats, s, prior, tol=TOL, **opts):
     cp, row, val = mats
     sysm = m.System(G.nx, G.ny, G.n_views, G.n_channels, cp, row, val, N, **opts)
     cfg = sysm.config
     assert cfg["sv_size"] == 8 and cfg["rows_per_agent"] > 1, cfg
-    x, info = sysm.solve(s.y, s.lam, prior, RHO, SIGMA, 20000, tol=TOL)
+    x, info = sysm.solve(s.y, s.lam, prior, RHO, SIGMA, 20000, tol=tol)
     sysm.close()
-    assert info.status == m.MACE_OK and info.residual < TOL, (info.status, info.residual)
+    assert info.status == m.MACE_OK and info.residual < tol, (info.status, info.residual)
     return x, info
 
 
@@ -103,7 +103,10 @@ def test_benchmark_shape_qggmrf_fp32(m, problem):
     xc, passes = O.centralized_icd(rtol=1e-9, max_passes=2000, mode=oracle.MODE_SURROGATE)
     assert passes < 2000
     prior = m.make_prior(1, SX, 2.0, 1.2, 1.0)
-    x32, i32 = _solve(m, mats, s, prior)
+    # the q-GGMRF iteration converges more slowly than the quadratic one
+    # (about 3000 iterations to r < 1e-7, which leaves NRMSE ~8e-5): stop
+    # at r < 4e-8, above the FP32 floor near 1.5e-8
+    x32, i32 = _solve(m, mats, s, prior, tol=4e-8)
     e32 = _nrmse(x32, xc)
     print(f"q-GGMRF FP32: {i32.iters} iterations, r {i32.residual:.2e}, nrmse {e32:.2e}",
           flush=True)
