@@ -287,6 +287,8 @@ static int check_pack_general(const mace_system* s, const HostPack& hp) {
       int rows = 0;
       for (int kl = 0; kl < kpad; ++kl) {
         const BandEnt& b = hp.band[asv * kpad + kl];
+        // the kernel reads entry gstart of an empty band
+        if (b.width == 0 && b.gstart != 0) return fail(MACE_E_MATRIX, "check: empty band with gstart %u", b.gstart);
         if (b.width == 0) continue;
         if (kl >= K) return fail(MACE_E_MATRIX, "check: band entry on a padding view");
         if ((int)b.lds_row + b.width > B) return fail(MACE_E_MATRIX, "check: band overruns its rows");

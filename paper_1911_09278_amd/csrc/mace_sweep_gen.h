@@ -41,6 +41,33 @@ __host__ __device__ inline size_t gen_row_lds_bytes(int bmax, int S) {
   return per_row > red ? per_row : red;
 }
 
+// Value of lane l of the lane's DPP row (16 lanes), for every lane of the row
+// (every lane of the row must be active).
+template <int L>
+__device__ __forceinline__ uint32_t row_bcast_c(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150 | L, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t row_bcast(uint32_t v, int l) {
+  switch (l) {  // l is a constant in the unrolled loops that call this
+    case 0: return row_bcast_c<0>(v);
+    case 1: return row_bcast_c<1>(v);
+    case 2: return row_bcast_c<2>(v);
+    case 3: return row_bcast_c<3>(v);
+    case 4: return row_bcast_c<4>(v);
+    case 5: return row_bcast_c<5>(v);
+    case 6: return row_bcast_c<6>(v);
+    case 7: return row_bcast_c<7>(v);
+    case 8: return row_bcast_c<8>(v);
+    case 9: return row_bcast_c<9>(v);
+    case 10: return row_bcast_c<10>(v);
+    case 11: return row_bcast_c<11>(v);
+    case 12: return row_bcast_c<12>(v);
+    case 13: return row_bcast_c<13>(v);
+    case 14: return row_bcast_c<14>(v);
+    default: return row_bcast_c<15>(v);
+  }
+}
+
 // The lane's share of a general record: entries lr, lr + 16, ... of the
 // pixel's list, nzp / 16 <= NZL of them (the list's own padding holds 0 on
 // the task's dummy row).
@@ -124,39 +151,71 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
     const int z = raw >> kSlotShift;  // volumes: the task's slice
     const bool has_lo = a.vol_nz > 0 && z > 0, has_hi = a.vol_nz > 0 && z + 1 < a.vol_nz;
 
-    // ---- 1. stage the band view by view, 16 channels at a time ----
-    for (int k = 0; k < a.kpad; ++k) {
-      const BandEnt b = be[k];
-      for (int c = lr; c < b.width; c += kRowLanes) {
-        const uint32_t gi = b.gstart + (uint32_t)c;
-        const float ev = MODE == kSweep ? load_e(eag + gi) : 0.0f;
-        const float lv = MODE != kRefresh ? lam[gi] : 0.0f;
-        band[b.lds_row + c] = make_float2(ev, lv);
-        if (MODE == kSweep) e0l[b.lds_row + c] = ev;
+    // ---- 1. stage the band, 16 views at a time: each lane loads one
+    //         view's band entry, every view's entry is broadcast over the
+    //         row, and the 16 views' first 16 channels are loaded before
+    //         any is written (channels past 16 of a wide view follow) ----
+    for (int kb = 0; kb < a.kpad; kb += kRowLanes) {
+      uint2 mine = make_uint2(0u, 0u);  // (gstart, lds_row | width << 16); 0: no view
+      if (kb + lr < a.kpad) mine = *reinterpret_cast<const uint2*>(be + kb + lr);
+      float ev[kRowLanes], lv[kRowLanes];
+      uint32_t lw[kRowLanes], gs[kRowLanes];
+#pragma unroll
+      for (int k = 0; k < kRowLanes; ++k) {
+        gs[k] = row_bcast(mine.x, k);
+        lw[k] = row_bcast(mine.y, k);
+        const int wd = (int)(lw[k] >> 16);
+        // lanes past the band (and views past kpad: gstart 0) read a valid
+        // entry of the agent's block and write nothing
+        const uint32_t gi = gs[k] + (uint32_t)min(lr, max(wd - 1, 0));
+        ev[k] = MODE == kSweep ? load_e(eag + gi) : 0.0f;
+        lv[k] = MODE != kRefresh ? lam[gi] : 0.0f;
+      }
+#pragma unroll
+      for (int k = 0; k < kRowLanes; ++k) {
+        const int wd = (int)(lw[k] >> 16), lrow = (int)(lw[k] & 0xFFFFu);
+        if (lr < wd) {
+          band[lrow + lr] = make_float2(ev[k], lv[k]);
+          if (MODE == kSweep) e0l[lrow + lr] = ev[k];
+        }
+        for (int c = lr + kRowLanes; c < wd; c += kRowLanes) {
+          const uint32_t gi = gs[k] + (uint32_t)c;
+          const float e2 = MODE == kSweep ? load_e(eag + gi) : 0.0f;
+          const float l2 = MODE != kRefresh ? lam[gi] : 0.0f;
+          band[lrow + c] = make_float2(e2, l2);
+          if (MODE == kSweep) e0l[lrow + c] = e2;
+        }
       }
     }
     if (lr < 2) band[B + lr] = make_float2(0.0f, 0.0f);
+    // halo, v, theta2 (and the axial neighbours): fixed trip counts per
+    // lane, unrolled so that several loads are in flight before the writes
     if (MODE != kTheta2) {
-      for (int c = lr; c < HS * HS; c += kRowLanes) {
+#pragma unroll 8
+      for (int u = 0; u < NHC / kRowLanes; ++u) {
+        const int c = u * kRowLanes + lr;  // cells past HS * HS are padding
         const int hi = c / HS, hj = c - hi * HS;
         const int iy = y0 - 1 + hi, ix = x0 - 1 + hj;
-        const bool in = iy >= 0 && iy < a.ny && ix >= 0 && ix < a.nx;
-        halo[c] = in ? cX[img + (size_t)iy * a.nx + ix] : 0.0f;
+        const bool in = c < HS * HS && iy >= 0 && iy < a.ny && ix >= 0 && ix < a.nx;
+        const int iyc = min(max(iy, 0), a.ny - 1), ixc = min(max(ix, 0), a.nx - 1);
+        const float xv = cX[img + (size_t)iyc * a.nx + ixc];
+        halo[c] = in ? xv : 0.0f;
       }
     }
     if (MODE == kSweep) {
-      for (int p = lr; p < npix; p += kRowLanes) {
-        const int pi = p / sw, pj = p - (p / sw) * sw;
+      gptr<const float> Xlo = glb((const float*)a.slots[has_lo ? z - 1 : z].X);
+      gptr<const float> Xhi = glb((const float*)a.slots[has_hi ? z + 1 : z].X);
+#pragma unroll 8
+      for (int u = 0; u < S * S / kRowLanes; ++u) {
+        // S * S is a multiple of 16; entries past npix (ragged SVs) repeat
+        // the last pixel and are never read
+        const int p = u * kRowLanes + lr;
+        const int pc = min(p, npix - 1);
+        const int pi = pc / sw, pj = pc - (pc / sw) * sw;
         const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
         vv[p] = 2.0f * cwbar[pix] - cw[img + pix];
         t2[p] = cth2[img + pix];
-      }
-      if (a.vol_nz > 0) {
-        gptr<const float> Xlo = glb((const float*)a.slots[has_lo ? z - 1 : z].X);
-        gptr<const float> Xhi = glb((const float*)a.slots[has_hi ? z + 1 : z].X);
-        for (int p = lr; p < npix; p += kRowLanes) {
-          const int pi = p / sw, pj = p - (p / sw) * sw;
-          const size_t pix = (size_t)(y0 + pi) * a.nx + x0 + pj;
+        if (a.vol_nz > 0) {
           xlo[p] = has_lo ? Xlo[img + pix] : 0.0f;
           xhi[p] = has_hi ? Xhi[img + pix] : 0.0f;
         }
@@ -252,14 +311,21 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
       }
     }
 
-    // ---- 3. write back, view by view ----
+    // ---- 3. write back, 16 views at a time (entries broadcast as in the
+    //         staging) ----
     if (MODE != kTheta2) {
-      for (int k = 0; k < a.kpad; ++k) {
-        const BandEnt b = be[k];
-        for (int c = lr; c < b.width; c += kRowLanes) {
-          float d = band[b.lds_row + c].x;
-          if (MODE == kSweep) d -= e0l[b.lds_row + c];
-          add_e(eag + b.gstart + c, d);
+      for (int kb = 0; kb < a.kpad; kb += kRowLanes) {
+        uint2 mine = make_uint2(0u, 0u);
+        if (kb + lr < a.kpad) mine = *reinterpret_cast<const uint2*>(be + kb + lr);
+#pragma unroll
+        for (int k = 0; k < kRowLanes; ++k) {
+          const uint32_t g0 = row_bcast(mine.x, k), lw = row_bcast(mine.y, k);
+          const int wd = (int)(lw >> 16), lrow = (int)(lw & 0xFFFFu);
+          for (int c = lr; c < wd; c += kRowLanes) {
+            float d = band[lrow + c].x;
+            if (MODE == kSweep) d -= e0l[lrow + c];
+            add_e(eag + g0 + c, d);
+          }
         }
       }
     }
