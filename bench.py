@@ -269,6 +269,42 @@ def leg_time_to_tol(sysm, w8, m, mi, torch, y, lam, sigma, tol=1e-4, max_iters=3
     return out
 
 
+def leg_volume(m, mi, torch, iters=60, nz=16, b_axial=0.5):
+    """A volume of 16 slices of 256x256 (360 views, 368 channels, 8 agents,
+    q-GGMRF) with the 3-D prior's axial cliques (b_axial = 0.5 against the
+    in-plane weights' sum of 1), `iters` Mann iterations through
+    mace_solve_volume (host arrays in and out), with the compact and with
+    the general records, against the same 16 slices solved as an independent
+    batch (mace_solve_batch) with the same records."""
+    w = mi.WORKLOADS["serve256"]
+    g = w.geom
+    sigma = 2e-4
+    cp, row, val = mi.system_matrix(g)
+    scans = [mi.scan(g, w.seed + 100 + z) for z in range(nz)]
+    y = np.stack([sc.y for sc in scans])
+    lam = np.stack([sc.lam for sc in scans])
+    prior = m.make_prior(w.prior_kind, w.sigma_x, w.p, w.q, w.T)
+    out = {"workload": f"volume256: {nz} slices of 256x256, 360 views, 368 channels, 8 agents, "
+                       f"q-GGMRF, b_axial={b_axial}", "mann_iters": iters, "sigma": sigma}
+    for fmt, name in ((1, "compact"), (2, "general")):
+        sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents, format=fmt)
+        sysm.set_relaxation(0.5)
+        sysm.solve_volume(y, lam, prior, b_axial, w.rho, sigma, 2)  # warm-up
+        t0 = time.perf_counter()
+        _, info = sysm.solve_volume(y, lam, prior, b_axial, w.rho, sigma, iters)
+        tv = time.perf_counter() - t0
+        sysm.solve_batch(list(y), list(lam), prior, w.rho, sigma, 2)
+        t0 = time.perf_counter()
+        infos = sysm.solve_batch(list(y), list(lam), prior, w.rho, sigma, iters)[1]
+        tb = time.perf_counter() - t0
+        out[name] = {"volume_ms_per_mann_iter": tv / iters * 1e3, "volume_residual": info.residual,
+                     "volume_voxel_updates_per_s": iters * w.n_agents * g.n * nz / tv,
+                     "batch_ms_per_mann_iter": tb / iters * 1e3,
+                     "batch_mean_residual": float(np.mean([i.residual for i in infos]))}
+        sysm.close()
+    return out
+
+
 def leg_serve(m, mi, torch, n_arrivals=300, tol=1e-4, max_iters=3000):
     """Served 256x256 scans (360 views, 368 channels, 8 agents, q-GGMRF, each
     its own phantom) stopping at r < tol: the one-scan-at-a-time FP32 path
@@ -781,13 +817,15 @@ def main():
                     help="only the headline scan (no slices / FP16 / serving legs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
-    ap.add_argument("--mode", default="scan", choices=("scan", "slices", "serve", "fp16", "pnp", "study"),
+    ap.add_argument("--mode", default="scan",
+                    choices=("scan", "slices", "serve", "fp16", "pnp", "study", "volume"),
                     help="scan: the headline one-scan benchmark (default); slices: 64 "
                          "512x512 slices sharing one matrix, batched vs one at a time; "
                          "serve: Poisson arrivals of mixed-size scans through the server; "
                          "fp16: 1024x1024 FP16 matrix values vs FP32; "
                          "pnp: MACE-PnP with the binomial stand-in denoiser; "
-                         "study: equits to convergence vs rho and vs the number of agents")
+                         "study: equits to convergence vs rho and vs the number of agents; "
+                         "volume: 16 coupled 256x256 slices vs the same slices as a batch")
     ap.add_argument("--scans", type=int, default=30, help="serve: number of arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
     ap.add_argument("--slices", type=int, default=64, help="slices: batch size")
@@ -819,7 +857,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.mode != "scan":
         out = {"slices": bench_slices, "serve": bench_serve, "fp16": bench_fp16,
-               "pnp": bench_pnp, "study": bench_study}[args.mode](args, m, mi, torch)
+               "pnp": bench_pnp, "study": bench_study,
+               "volume": lambda a, *r: leg_volume(*r, a.iters)}[args.mode](args, m, mi, torch)
         print(json.dumps(out), flush=True)
         return
     w8 = mi.WORKLOADS["scan512"]
@@ -912,6 +951,7 @@ def main():
         sysm.close()
         extra["fp16_1024"] = leg_fp16(m, mi, torch, args.iters)
         extra["serve256"] = leg_serve(m, mi, torch)
+        extra["volume256"] = leg_volume(m, mi, torch, args.iters)
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 

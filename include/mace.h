@@ -194,8 +194,8 @@ int mace_solve_resume(mace_system* sys, const float* y, const float* lambda,
  * reads do not change while its slice sweeps).
  * y, lambda: host, float[nz][n_views * n_channels] (slice z's sinogram in
  *   global row order); x_out: host, float[nz][nx * ny].
- * 1 <= nz <= 128; b_axial >= 0 (0: independent slices).  The system must
- * hold the general records (loaded with mace_opts.format = 2), else
+ * 1 <= nz <= 128; b_axial >= 0 (0: independent slices).  Either record
+ * format; the system must hold FP32 matrix values (precision 0), else
  * MACE_E_ARG; other arguments, results and errors as mace_solve
  * (info->residual is the stacked r_k).  The slices occupy scan slots 0 ..
  * nz - 1: mace_get_slot_state(sys, z, ...) returns slice z's (w, X).

@@ -484,8 +484,8 @@ int solve_volume_impl(mace_system* s, int nz, const float* y, const float* lam,
                       int max_iters, double tol, float* x_out, mace_info* info) {
   int rc = check_prior(pr);
   if (rc) return rc;
-  if (s->format != 1)
-    return fail(MACE_E_ARG, "volumes need the general record format (load the system with format 2)");
+  if (s->precision != 0)
+    return fail(MACE_E_ARG, "volumes run with FP32 matrix values (load the system with precision 0)");
   if (nz < 1 || nz > kMaxScanSlots) return fail(MACE_E_ARG, "nz must be in [1, %d]", kMaxScanSlots);
   if (!(b_axial >= 0) || !std::isfinite(b_axial)) return fail(MACE_E_ARG, "b_axial must be >= 0");
   if (!(rho > 0 && rho < 1)) return fail(MACE_E_ARG, "rho must be in (0, 1)");

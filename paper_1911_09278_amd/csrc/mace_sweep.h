@@ -89,6 +89,7 @@ template <int SL>
 struct Rec {
   float2 val[SL];
   int off[SL];  // row delta within the view's band
+  float ax;     // volumes: the axial neighbour of lanes 9 and 10
 };
 
 __device__ __forceinline__ int row_delta(uint32_t word, int lr) {
@@ -186,7 +187,11 @@ struct Occupancy {
   static constexpr int waves = SL <= 3 ? 2 : 1;
 };
 
-template <int SL, int MODE, int S, bool F16>
+// VOL: the slots are the slices of a volume, and lanes 9 and 10 add the
+// axial cliques to the agent's voxels of slices z - 1 and z + 1 (read with
+// the records, a pixel step ahead; the other parity's slices do not change
+// during the launch).
+template <int SL, int MODE, int S, bool F16, bool VOL = false>
 __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel(SvArgs a) {
   constexpr int HS = S + 2;
   constexpr int KP = SL * kRowLanes;                                 // view slots
@@ -213,7 +218,10 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
   const int ndi = (lr < 3) ? -1 : (lr < 5 ? 0 : 1);
   const int ndj = (lr == 0 || lr == 3 || lr == 5) ? -1 : ((lr == 1 || lr == 6) ? 0 : 1);
   // lanes 8-15 carry no neighbour: zero weight, offset 0 (their own cell)
-  const float nbw = lr < 8 ? ((ndi != 0 && ndj != 0) ? a.bdiag : a.bedge) * a.invN : 0.0f;
+  // lanes 9 and 10 of a volume: the axial neighbours below and above
+  const bool axial = VOL && (lr == 9 || lr == 10);
+  const float nbw = lr < 8 ? ((ndi != 0 && ndj != 0) ? a.bdiag : a.bedge) * a.invN
+                           : (axial ? a.baxial * a.invN : 0.0f);
   const int noff = lr < 8 ? ndi * HS + ndj : 0;
   const int ndi8 = lr < 8 ? ndi : 0, ndj8 = lr < 8 ? ndj : 0;
   const float proxw = lr == 8 ? a.is2 : 0.0f;  // lane 8 adds the prox term
@@ -225,6 +233,7 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
   // Header of a task: everything its id determines (issued one task ahead).
   struct Hdr {
     int task;  // agent * n_sv + sv, or -1
+    int slot;  // the task's slot (the slice of a volume)
     gptr<float> e;
     gptr<const float> lam;
     gptr<float> X, w, th2;
@@ -237,7 +246,8 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
     h.task = -1;
     if (raw < 0) return;
     const int task = raw & ((1 << kSlotShift) - 1);
-    const SlotDesc* sd = a.slots + (raw >> kSlotShift);
+    h.slot = raw >> kSlotShift;
+    const SlotDesc* sd = a.slots + h.slot;
     const int agent = task / a.n_sv;
     const int sv = task - agent * a.n_sv;
     const size_t agent_sv = (size_t)agent * a.n_sv + sv;
@@ -377,6 +387,14 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
     gptr<float> cw = cur.w;
     gptr<float> cth2 = cur.th2;
     gptr<double> cpart = cur.part;
+    // volumes: the slices below and above (own slice where there is none;
+    // those lanes' weight is then 0)
+    const bool has_lo = VOL && cur.slot > 0, has_hi = VOL && cur.slot + 1 < a.vol_nz;
+    const int zn = lr == 9 ? (has_lo ? cur.slot - 1 : cur.slot)
+                           : (lr == 10 && has_hi ? cur.slot + 1 : cur.slot);
+    gptr<const float> axp = nullptr;
+    if constexpr (VOL) axp = glb((const float*)a.slots[zn].X) + img;
+    const float ax_in = (lr == 9 ? has_lo : has_hi) ? 1.0f : 0.0f;
 
     // ---- 2. pixel loop: records prefetched kPrefetch pixels ahead ----
     const size_t rec0 = (size_t)agent * a.n + pix0;
@@ -399,11 +417,17 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
           p1[s2] = band[o[s2] + 1];
         }
         const float zs = halo[cidx];
-        const float nbv = halo[cidx + noff];
+        float nbv = halo[cidx + noff];
         const float vj = vv[j], tj = t2[j];
         // the neighbour lies in the image (lanes 8-15: weight 0 anyway)
         const int iy = y0 + pi + ndi8, ix = x0 + pj + ndj8;
-        const float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+        float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+        if constexpr (VOL) {
+          if (axial) {
+            nbv = cur.ax;
+            nin = ax_in;
+          }
+        }
         float part = 0.0f;
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2)
@@ -454,12 +478,19 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
       const uint32_t* db = a.adel + rec0 * (SL * 2) + (lr >> 3);
       Rec<SL> buf[S * S];
 #pragma unroll
-      for (int q = 0; q < kPrefetch; ++q)
+      for (int q = 0; q < kPrefetch; ++q) {
         load_rec_at<SL, F16>(vb, hb, sb, db, kstr, last_ok, lr, q, buf[q]);
+        if constexpr (VOL) buf[q].ax = axp[(size_t)(y0 + q / S) * a.nx + x0 + q % S];
+      }
 #pragma unroll
       for (int j = 0; j < S * S; ++j) {
-        if (j + kPrefetch < S * S)
+        if (j + kPrefetch < S * S) {
           load_rec_at<SL, F16>(vb, hb, sb, db, kstr, last_ok, lr, j + kPrefetch, buf[j + kPrefetch]);
+          if constexpr (VOL) {
+            const int q = j + kPrefetch;
+            buf[q].ax = axp[(size_t)(y0 + q / S) * a.nx + x0 + q % S];
+          }
+        }
         update(buf[j], j, j / S, j % S);
       }
     } else {
@@ -467,6 +498,7 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
       for (int j = 0; j < npix; ++j) {
         Rec<SL> cur;
         load_rec<SL, F16>(a, rec0 + j, lr, cur);
+        if constexpr (VOL) cur.ax = axp[(size_t)(y0 + j / sw) * a.nx + x0 + j - (j / sw) * sw];
         update(cur, j, j / sw, j - (j / sw) * sw);
       }
     }
@@ -557,20 +589,20 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
 }
 
 
-template <int MODE, int SV, bool F16V>
+template <int MODE, int SV, bool F16V, bool VOL = false>
 inline hipError_t launch_mode(const SvArgs& a, int slots, int grid, size_t lds, hipStream_t st) {
   switch (slots) {
 #define MACE_CASE(SLV)                                                                   \
   case SLV: {                                                                            \
     static std::atomic<bool> attr_set{false};                                            \
     if (!attr_set.load(std::memory_order_acquire)) {                                     \
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel<SLV, MODE, SV, F16V>), \
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel<SLV, MODE, SV, F16V, VOL>), \
                                          hipFuncAttributeMaxDynamicSharedMemorySize,     \
                                          (int)kMaxLdsBytes);                              \
       if (e != hipSuccess) return e;                                                     \
       attr_set.store(true, std::memory_order_release);                                   \
     }                                                                                    \
-    hipLaunchKernelGGL((sv_kernel<SLV, MODE, SV, F16V>), dim3(grid), dim3(a.rpb * kRowLanes), lds, st, a); \
+    hipLaunchKernelGGL((sv_kernel<SLV, MODE, SV, F16V, VOL>), dim3(grid), dim3(a.rpb * kRowLanes), lds, st, a); \
     break;                                                                               \
   }
     MACE_CASE(1)
@@ -591,6 +623,9 @@ inline hipError_t launch_mode(const SvArgs& a, int slots, int grid, size_t lds, 
 template <int SV, bool F16V>
 inline hipError_t launch_s(const SvArgs& a, int mode, int slots, int grid, size_t lds,
                            hipStream_t st) {
+  if constexpr (!F16V) {  // volumes run with FP32 values
+    if (mode == kSweep && a.vol_nz > 0) return launch_mode<kSweep, SV, false, true>(a, slots, grid, lds, st);
+  }
   if (mode == kSweep) return launch_mode<kSweep, SV, F16V>(a, slots, grid, lds, st);
   if (mode == kTheta2) return launch_mode<kTheta2, SV, F16V>(a, slots, grid, lds, st);
   return launch_mode<kRefresh, SV, F16V>(a, slots, grid, lds, st);

@@ -4,7 +4,9 @@ against the oracle's 3-D problem.
 A volume is nz slices measured by one 2-D matrix; the prior adds the axial
 cliques (z, s)-(z + 1, s) with weight b_axial to every slice's 8 in-plane
 cliques, and partial-update MACE runs over the stacked voxels.  The GPU
-sweeps each colour phase twice, the even slices and then the odd ones.
+sweeps each colour phase twice, the even slices and then the odd ones, with
+either record format (compact: the axial neighbours are read a pixel step
+ahead with the records; general: staged with the super-voxel).
 
 1. Sequential schedule (one row per agent): the trajectory equals the
    oracle's, run in the GPU's visiting order (colour c, then the even
@@ -61,21 +63,25 @@ def _volume_order(sysm, g, nz, S):
 
 
 SEQ_CASES = [
-    # geometry, nz, N, prior kind, sigma_x, q, b_axial, sigma, S, iterations
-    (mi.Geometry(24, 24, 24, 36), 3, 2, 1, 0.002, 1.2, 0.5, 0.001, 8, 4),
-    (mi.Geometry(20, 18, 30, 30), 4, 3, 0, 0.003, 2.0, 0.25, 0.002, 4, 3),
-    (mi.Geometry(16, 16, 16, 24), 2, 2, 1, 0.002, 1.2, 1.0, 0.001, 4, 3),
+    # geometry, nz, N, prior kind, sigma_x, q, b_axial, sigma, S, iterations, record format
+    (mi.Geometry(24, 24, 24, 36), 3, 2, 1, 0.002, 1.2, 0.5, 0.001, 8, 4, 2),
+    (mi.Geometry(20, 18, 30, 30), 4, 3, 0, 0.003, 2.0, 0.25, 0.002, 4, 3, 2),
+    (mi.Geometry(16, 16, 16, 24), 2, 2, 1, 0.002, 1.2, 1.0, 0.001, 4, 3, 2),
+    (mi.Geometry(24, 24, 24, 36), 3, 2, 1, 0.002, 1.2, 0.5, 0.001, 8, 4, 1),
+    (mi.Geometry(20, 18, 30, 30), 5, 3, 0, 0.003, 2.0, 0.25, 0.002, 4, 3, 1),   # ragged SVs
+    (mi.Geometry(16, 16, 16, 24), 2, 2, 1, 0.002, 1.2, 1.0, 0.001, 8, 3, 1),
 ]
 
 
 @pytest.mark.parametrize("case", SEQ_CASES,
-                         ids=lambda c: f"{c[0].nx}x{c[0].ny}z{c[1]}_N{c[2]}_k{c[3]}_ba{c[6]}")
+                         ids=lambda c: f"{c[0].nx}x{c[0].ny}z{c[1]}_N{c[2]}_k{c[3]}_ba{c[6]}_S{c[8]}_f{c[10]}")
 def test_volume_sequential_trajectory_matches_oracle(m, case):
-    g, nz, N, kind, sx, q, ba, sigma, S, iters = case
+    g, nz, N, kind, sx, q, ba, sigma, S, iters, fmt = case
     (cp, row, val), y, lam, O = _volume(g, nz, 301 + g.nx, N, kind, sx, ba, q)
-    print(f"case {g} nz={nz} N={N} b_axial={ba}", flush=True)
+    print(f"case {g} nz={nz} N={N} b_axial={ba} S={S} format={fmt}", flush=True)
     sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=S,
-                    rows_per_agent=1, format=2)
+                    rows_per_agent=1, format=fmt)
+    assert sysm.config["format"] == fmt
     prior = m.make_prior(kind, sx, 2.0, q, 1.0)
     x, info = sysm.solve_volume(y, lam, prior, ba, 0.8, sigma, iters)
     order = _volume_order(sysm, g, nz, S)
@@ -92,31 +98,42 @@ def test_volume_sequential_trajectory_matches_oracle(m, case):
     assert abs(info.residual - ref["resid"][-1]) <= 1e-3 * ref["resid"][-1] + 1e-7
 
 
-def test_volume_concurrent_fixed_point_is_the_map(m):
+@pytest.fixture(scope="module")
+def volume_map():
     g = mi.Geometry(64, 64, 48, 96)
-    nz, N, sx, ba, sigma = 4, 4, 0.001, 0.5, 5e-4
+    nz, N, sx, ba = 4, 4, 0.001, 0.5
     (cp, row, val), y, lam, O = _volume(g, nz, 17, N, 0, sx, ba)
     xmap, _, rel = O.map_cg(rtol=1e-13)
     assert rel <= 1e-12
-    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, format=2)
+    return g, nz, N, sx, ba, (cp, row, val), y, lam, xmap
+
+
+@pytest.mark.parametrize("fmt", [2, 1])
+def test_volume_concurrent_fixed_point_is_the_map(m, volume_map, fmt):
+    g, nz, N, sx, ba, (cp, row, val), y, lam, xmap = volume_map
+    sigma = 5e-4
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, format=fmt)
+    assert sysm.config["format"] == fmt
     assert sysm.config["rows_per_agent"] > 1
     sysm.set_relaxation(0.5)
     # r < 1e-7: the concurrent schedule's FP32 iterates level off near
     # r = 1e-8, and 1e-7 already leaves NRMSE ~2e-5 to the MAP
     x, info = sysm.solve_volume(y, lam, m.make_prior(0, sx), ba, 0.8, sigma, 20000, tol=1e-7)
     e = float(np.linalg.norm(x.reshape(-1).astype(np.float64) - xmap) / np.linalg.norm(xmap))
-    print(f"volume {g} nz={nz}: {info.iters} iterations, r {info.residual:.2e}, nrmse {e:.2e}",
+    print(f"volume {g} nz={nz} format {fmt}: {info.iters} iterations, r {info.residual:.2e}, "
+          f"nrmse {e:.2e}",
           flush=True)
     assert info.status == m.MACE_OK
     assert e <= 1e-4
 
 
-def test_volume_without_axial_cliques_is_independent_slices(m):
+@pytest.mark.parametrize("fmt", [2, 1])
+def test_volume_without_axial_cliques_is_independent_slices(m, fmt):
     g = mi.Geometry(24, 24, 24, 36)
     nz, N, sx, sigma = 3, 2, 0.002, 0.001
     (cp, row, val), y, lam, _ = _volume(g, nz, 41, N, 1, sx, 0.0, 1.2)
     sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=8,
-                    rows_per_agent=1, format=2)
+                    rows_per_agent=1, format=fmt)
     prior = m.make_prior(1, sx, 2.0, 1.2, 1.0)
     xv, _ = sysm.solve_volume(y, lam, prior, 0.0, 0.8, sigma, 5)
     for z in range(nz):
@@ -128,10 +145,10 @@ def test_volume_argument_errors(m):
     g = mi.Geometry(24, 24, 24, 36)
     (cp, row, val), y, lam, _ = _volume(g, 2, 5, 2, 0, 0.002, 0.5)
     prior = m.make_prior(0, 0.002)
-    compact = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, format=1)
+    fp16 = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, precision=1)
     with pytest.raises(m.MaceError) as ei:
-        compact.solve_volume(y, lam, prior, 0.5, 0.8, 0.001, 2)
-    assert ei.value.code == m.MACE_E_ARG and "general record format" in str(ei.value)
+        fp16.solve_volume(y, lam, prior, 0.5, 0.8, 0.001, 2)
+    assert ei.value.code == m.MACE_E_ARG and "FP32 matrix values" in str(ei.value)
     general = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, format=2)
     with pytest.raises(m.MaceError) as ei:
         general.solve_volume(y, lam, prior, -1.0, 0.8, 0.001, 2)
