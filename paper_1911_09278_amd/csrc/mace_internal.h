@@ -98,9 +98,9 @@ hipError_t launch_sv_s8f16(const SvArgs& a, int mode, int slots, int grid, size_
 
 // Launchers (defined in mace_kernels.hip).
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st);
-// Rows per workgroup: the most of 16, 8, 4 (general records: down to 1)
-// whose LDS fits in 160 KiB (0 if none does), and the LDS bytes of such a
-// workgroup.
+// Rows per workgroup: of 16, 8 and 4, the one that keeps the most rows of a
+// CU's 160 KiB of LDS resident (general records: down to 1 when not even 4
+// fit; 0 if none does), and the LDS bytes of such a workgroup.
 int sv_rows_per_block(int bmax, int S, int kpad, int format);
 size_t sv_lds_bytes(int bmax, int S, int kpad, int format);
 // Doubles the epilogue needs after a slot's task partials.

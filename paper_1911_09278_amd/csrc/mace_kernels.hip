@@ -14,9 +14,23 @@ static size_t row_bytes(int bmax, int S, int kpad, int format) {
 }
 
 int sv_rows_per_block(int bmax, int S, int kpad, int format) {
-  const int lo = format == 1 ? 1 : 4;
-  for (int rpb = kMaxRowsPerBlock; rpb >= lo; rpb /= 2)
-    if ((size_t)rpb * row_bytes(bmax, S, kpad, format) <= kMaxLdsBytes) return rpb;
+  const size_t row = row_bytes(bmax, S, kpad, format);
+  // whole waves (16, 8 or 4 rows): the size that keeps the most rows of a
+  // CU's LDS resident (the larger one on a tie)
+  int best = 0;
+  size_t best_rows = 0;
+  for (int rpb = kMaxRowsPerBlock; rpb >= 4; rpb /= 2) {
+    if ((size_t)rpb * row > kMaxLdsBytes) continue;
+    const size_t resident = kMaxLdsBytes / ((size_t)rpb * row) * rpb;
+    if (resident > best_rows) {
+      best = rpb;
+      best_rows = resident;
+    }
+  }
+  if (best > 0 || format != 1) return best;
+  // general records: rows too large for four to a workgroup
+  for (int rpb = 2; rpb >= 1; rpb /= 2)
+    if ((size_t)rpb * row <= kMaxLdsBytes) return rpb;
   return 0;
 }
 

@@ -148,14 +148,19 @@ def test_concurrent_fixed_point_is_the_map(m):
 
 def test_concurrent_many_views_fixed_point_is_the_map(m):
     """75 views per agent with 8x8 super-voxels: bands too large for 16 rows
-    per workgroup, so the concurrent schedule runs 8-row workgroups; its
-    fixed point is still the MAP (dense Cholesky, quadratic prior)."""
+    per workgroup, so the concurrent schedule runs smaller workgroups (4
+    rows: three of them per CU keep 12 rows resident, against 8 in one
+    8-row workgroup); its fixed point is still the MAP (dense Cholesky,
+    quadratic prior)."""
     from tests import dense_ref as dr
     g = mi.Geometry(64, 64, 150, 96)
     N, sx, sigma = 2, 0.001, 3e-4
     (cp, row, val), s, va, O = _setup(g, 29, N, 0, sx)
     lds = m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=8)
-    assert 80 * 1024 < lds <= 160 * 1024  # more than 16 rows of it would not fit
+    # a row of this band takes about 11 KB (75 views of ~10 channels at
+    # 12 B), so a workgroup of 4 rows takes more than 40 KB, and 16 rows
+    # (176 KB) would not fit in 160 KiB
+    assert 40 * 1024 < lds <= 80 * 1024
     A = dr.dense_A(g, cp, row, val)
     xmap = dr.map_quadratic(A, s.lam.astype(np.float64), s.y.astype(np.float64),
                             dr.laplacian(g.nx, g.ny), sx)
