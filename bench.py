@@ -284,8 +284,14 @@ def leg_volume(m, mi, torch, iters=60, nz=16, b_axial=0.5):
     y = np.stack([sc.y for sc in scans])
     lam = np.stack([sc.lam for sc in scans])
     prior = m.make_prior(w.prior_kind, w.sigma_x, w.p, w.q, w.T)
+    nnz = int(cp[-1])
+    rows = g.n_views * g.n_channels
+    # the matrix once per colour phase and slice parity (shared by that
+    # parity's slices), each slice's state and sinogram once per iteration
+    hbm_floor_ms = (2 * nnz * 8 + nz * (w.n_agents * g.n * 20 + rows * 12)) / 8e12 * 1e3
     out = {"workload": f"volume256: {nz} slices of 256x256, 360 views, 368 channels, 8 agents, "
-                       f"q-GGMRF, b_axial={b_axial}", "mann_iters": iters, "sigma": sigma}
+                       f"q-GGMRF, b_axial={b_axial}", "mann_iters": iters, "sigma": sigma,
+           "hbm_floor_ms_per_mann_iter": hbm_floor_ms}
     for fmt, name in ((1, "compact"), (2, "general")):
         sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, w.n_agents, format=fmt)
         sysm.set_relaxation(0.5)
