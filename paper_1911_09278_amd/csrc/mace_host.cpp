@@ -202,6 +202,7 @@ static int repack_general(mace_system* s, const int64_t* cp, const int32_t* row,
     for (size_t k = 0; k < s->views[a].size(); ++k) local[s->views[a][k]] = (int)k;
   std::atomic<int> err{0};
   std::atomic<int> bmax{0};
+  std::atomic<int> wmaxa{0};
   const int nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<std::thread> th;
   for (int t = 0; t < nth; ++t)
@@ -239,6 +240,9 @@ static int repack_general(mace_system* s, const int64_t* cp, const int32_t* row,
               return;
             }
             hp.band[asv * kpad + kl] = b;
+            int cw = wmaxa.load();
+            while (b.width > cw && !wmaxa.compare_exchange_weak(cw, b.width)) {
+            }
           }
           // views that miss the SV, and padding views: width 0 on the dummy rows
           for (int kl = 0; kl < kpad; ++kl)
@@ -271,6 +275,7 @@ static int repack_general(mace_system* s, const int64_t* cp, const int32_t* row,
   if (err == 3) return fail(MACE_E_MATRIX, "super-voxel band exceeds 65533 rows; use a smaller sv_size");
   s->bmax = (bmax.load() + 1) & ~1;
   if (s->bmax < 2) s->bmax = 2;
+  s->wmax = wmaxa.load();
   finish_layout(s, hp);
   return MACE_OK;
 }
@@ -290,6 +295,9 @@ static int check_pack_general(const mace_system* s, const HostPack& hp) {
         // the kernel reads entry gstart of an empty band
         if (b.width == 0 && b.gstart != 0) return fail(MACE_E_MATRIX, "check: empty band with gstart %u", b.gstart);
         if (b.width == 0) continue;
+        // the kernel keeps the staged e in registers, one chunk per view,
+        // when wmax says every band fits 16 lanes
+        if (b.width > s->wmax) return fail(MACE_E_MATRIX, "check: band of %d channels above wmax %d", b.width, s->wmax);
         if (kl >= K) return fail(MACE_E_MATRIX, "check: band entry on a padding view");
         if ((int)b.lds_row + b.width > B) return fail(MACE_E_MATRIX, "check: band overruns its rows");
         if ((int64_t)b.gstart / s->n_ch != kl || ((int64_t)b.gstart + b.width - 1) / s->n_ch != kl)
@@ -556,7 +564,7 @@ static int check_pack(const mace_system* s, const HostPack& hp) {
 // 79 KB each for the 45-view workloads), fewer when a row's band, halo and
 // scratch would not fit 16 to the 160 KiB of LDS (many views per agent).
 static int pick_rows_per_block(mace_system* s) {
-  s->rpb = sv_rows_per_block(s->bmax, s->S, s->kpad, s->format);
+  s->rpb = sv_rows_per_block(s->bmax, s->S, s->kpad, s->format, s->wmax, s->nzp);
   if (s->rpb == 0)
     return fail(MACE_E_ARG,
                 "a super-voxel band of %d rows needs more than 40 KiB of LDS per row; %s", s->bmax,
@@ -917,7 +925,7 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
     }
     if (only >= 2) break;
   }
-  if (lds_bytes) *lds_bytes = (int64_t)sv_lds_bytes(s.bmax, s.S, s.kpad, s.format);
+  if (lds_bytes) *lds_bytes = (int64_t)sv_lds_bytes(s.bmax, s.S, s.kpad, s.format, s.wmax, s.nzp, false);
   return MACE_OK;
 }
 

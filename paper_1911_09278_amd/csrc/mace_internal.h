@@ -101,8 +101,9 @@ hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds,
 // Rows per workgroup: of 16, 8 and 4, the one that keeps the most rows of a
 // CU's 160 KiB of LDS resident (general records: down to 1 when not even 4
 // fit; 0 if none does), and the LDS bytes of such a workgroup.
-int sv_rows_per_block(int bmax, int S, int kpad, int format);
-size_t sv_lds_bytes(int bmax, int S, int kpad, int format);
+int sv_rows_per_block(int bmax, int S, int kpad, int format, int wmax, int nzp);
+// vol: a volume's launches (the general records stage the axial neighbours)
+size_t sv_lds_bytes(int bmax, int S, int kpad, int format, int wmax, int nzp, bool vol);
 // Doubles the epilogue needs after a slot's task partials.
 size_t epilogue_scratch_doubles();
 // The epilogue of each slot: consensus w-bar and the FP64 residual; with

@@ -9,12 +9,15 @@
 
 namespace mace {
 
-static size_t row_bytes(int bmax, int S, int kpad, int format) {
-  return format == 1 ? gen_row_lds_bytes(bmax, S) : row_lds_bytes(bmax, S, kpad);
+static size_t row_bytes(int bmax, int S, int kpad, int format, int wmax, int nzp, bool vol) {
+  return format == 1 ? gen_row_lds_bytes(bmax, S, gen_e0_in_regs(kpad, wmax, nzp), vol)
+                     : row_lds_bytes(bmax, S, kpad);
 }
 
-int sv_rows_per_block(int bmax, int S, int kpad, int format) {
-  const size_t row = row_bytes(bmax, S, kpad, format);
+int sv_rows_per_block(int bmax, int S, int kpad, int format, int wmax, int nzp) {
+  // sized for a volume's launches, the larger rows (a slice's launches then
+  // take less LDS per workgroup with the same rows)
+  const size_t row = row_bytes(bmax, S, kpad, format, wmax, nzp, true);
   // whole waves (16, 8 or 4 rows): the size that keeps the most rows of a
   // CU's LDS resident (the larger one on a tie)
   int best = 0;
@@ -34,9 +37,9 @@ int sv_rows_per_block(int bmax, int S, int kpad, int format) {
   return 0;
 }
 
-size_t sv_lds_bytes(int bmax, int S, int kpad, int format) {
-  const int rpb = sv_rows_per_block(bmax, S, kpad, format);
-  return (size_t)(rpb > 0 ? rpb : 1) * row_bytes(bmax, S, kpad, format);
+size_t sv_lds_bytes(int bmax, int S, int kpad, int format, int wmax, int nzp, bool vol) {
+  const int rpb = sv_rows_per_block(bmax, S, kpad, format, wmax, nzp);
+  return (size_t)(rpb > 0 ? rpb : 1) * row_bytes(bmax, S, kpad, format, wmax, nzp, vol);
 }
 
 hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds, hipStream_t st) {

@@ -105,7 +105,7 @@ Layout carve(const mace_system* s, uintptr_t base) {
 
 int phases(const mace_system* s, const mace::Schedule* sch, mace::SvArgs a, int mode,
            hipStream_t st) {
-  const size_t lds = mace::sv_lds_bytes(s->bmax, s->S, s->kpad, s->format);
+  const size_t lds = mace::sv_lds_bytes(s->bmax, s->S, s->kpad, s->format, s->wmax, s->nzp, a.vol_nz > 0);
   a.R = sch->R;
   for (int c = 0; c < 4; ++c) {
     a.tasks = sch->tasks[c].p;

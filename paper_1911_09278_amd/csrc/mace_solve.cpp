@@ -112,7 +112,7 @@ namespace {
 // from `slot_base`.
 int launch_phases(mace_system* s, const Schedule* sch, SvArgs a, int mode, hipStream_t st,
                   const SlotDesc* slot_base) {
-  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad, s->format);
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad, s->format, s->wmax, s->nzp, a.vol_nz > 0);
   a.R = sch->R;
   a.slots = slot_base;
   for (int c = 0; c < 4; ++c) {
@@ -131,7 +131,7 @@ int launch_phases(mace_system* s, const Schedule* sch, SvArgs a, int mode, hipSt
 // a phase does not matter).
 int enqueue_iteration(mace_system* s, Batch& b, const Schedule* sch, int n_slots, SvArgs a,
                       int sweeps, int prec_mask, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad, s->format);
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad, s->format, s->wmax, s->nzp, a.vol_nz > 0);
   a.R = sch->R;
   a.slots = b.table.p;
   if (ev0) HIP_OK(hipEventRecord(ev0, st));
@@ -518,7 +518,7 @@ int solve_volume_impl(mace_system* s, int nz, const float* y, const float* lam,
       rc = write_slot(s, b, i, 0, st);
       if (rc) return rc;
     }
-  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad, s->format);
+  const size_t lds = sv_lds_bytes(s->bmax, s->S, s->kpad, s->format, s->wmax, s->nzp, a.vol_nz > 0);
   a.slots = b.table.p;
   std::vector<double> sums((size_t)nz * 4);
   double r = 0.0;

@@ -31,11 +31,24 @@
 
 namespace mace {
 
+// The staged copy of e stays in registers (one per view slot and lane) when
+// every view's band fits one 16-lane chunk and the view slots fit what the
+// record registers leave (at most 256 VGPRs, no spill): 48 slots with records
+// of up to 128 entries, 32 with up to 256, 64 with records read in the loop.
+// Otherwise it lives in LDS.
+__host__ __device__ inline bool gen_e0_in_regs(int kpad, int wmax, int nzp) {
+  const int max_slots = nzp <= 8 * kRowLanes ? 3 * kRowLanes
+                        : nzp <= 16 * kRowLanes ? 2 * kRowLanes : 4 * kRowLanes;
+  return kpad <= max_slots && wmax <= kRowLanes;
+}
+
 // LDS bytes of one row of the general kernel: band (e, Lambda), the staged
-// e, the halo tile, and v / theta2 / the axial neighbours below and above of
-// the super-voxel's pixels.
-__host__ __device__ inline size_t gen_row_lds_bytes(int bmax, int S) {
-  size_t per_row = (size_t)bmax * 12 + (size_t)halo_cells(S) * 4 + (size_t)S * S * 16;
+// e (unless it stays in registers), the halo tile, v / theta2 and, in a
+// volume's launches, the axial neighbours below and above of the
+// super-voxel's pixels.
+__host__ __device__ inline size_t gen_row_lds_bytes(int bmax, int S, bool e0_regs, bool vol) {
+  size_t per_row = (size_t)bmax * (e0_regs ? 8 : 12) + (size_t)halo_cells(S) * 4 +
+                   (size_t)S * S * (vol ? 16 : 8);
   per_row = (per_row + 7) & ~(size_t)7;
   const size_t red = kRowLanes * 3 * sizeof(double);
   return per_row > red ? per_row : red;
@@ -94,7 +107,9 @@ __device__ __forceinline__ void load_gen(const SvArgs& a, size_t rec0, int j, in
 // NZL > 0 (sweep mode only): records of at most 16 NZL entries, held in
 // registers and loaded two pixels ahead; NZL = 0: any length, read in the
 // pixel loop.
-template <int MODE, int S, int NZL>
+// E0N > 0 (sweep mode only, when gen_e0_in_regs): the staged e in E0N
+// registers per lane (E0N >= kpad).
+template <int MODE, int S, int NZL, int E0N>
 __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
   constexpr int HS = S + 2;
   constexpr int NHC = halo_cells(S);
@@ -103,11 +118,12 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
   const int lr = lane64 & 15;
   const int rib = threadIdx.x >> 4;  // row in block
   const int row = blockIdx.x * a.rpb + rib;
-  const size_t per_row = gen_row_lds_bytes(a.bmax, S);
+  const bool e0_regs = gen_e0_in_regs(a.kpad, a.wmax, a.nzp);
+  const size_t per_row = gen_row_lds_bytes(a.bmax, S, e0_regs, a.vol_nz > 0);
   char* base = smem + rib * per_row;
   float2* band = reinterpret_cast<float2*>(base);
-  float* e0l = reinterpret_cast<float*>(base + (size_t)a.bmax * 8);
-  float* halo = e0l + a.bmax;
+  float* e0l = reinterpret_cast<float*>(base + (size_t)a.bmax * 8);  // when !e0_regs
+  float* halo = e0l + (e0_regs ? 0 : a.bmax);
   float* vv = halo + NHC;
   float* t2 = vv + S * S;
   float* xlo = t2 + S * S;  // volumes: the agent's voxels in slices z - 1, z + 1
@@ -154,11 +170,14 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
     // ---- 1. stage the band, 16 views at a time: each lane loads one
     //         view's band entry, every view's entry is broadcast over the
     //         row, and the 16 views' first 16 channels are loaded before
-    //         any is written (channels past 16 of a wide view follow) ----
-    for (int kb = 0; kb < a.kpad; kb += kRowLanes) {
+    //         any is written (channels past 16 of a wide view follow); e as
+    //         staged goes to e0 (registers or LDS) for the write-back ----
+    // one batch of 16 views from view slot kb; ev receives the lane's
+    // staged e of each of them (its channel lr)
+    auto stage_batch = [&](int kb, float* ev) {
       uint2 mine = make_uint2(0u, 0u);  // (gstart, lds_row | width << 16); 0: no view
       if (kb + lr < a.kpad) mine = *reinterpret_cast<const uint2*>(be + kb + lr);
-      float ev[kRowLanes], lv[kRowLanes];
+      float lv[kRowLanes];
       uint32_t lw[kRowLanes], gs[kRowLanes];
 #pragma unroll
       for (int k = 0; k < kRowLanes; ++k) {
@@ -176,15 +195,34 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
         const int wd = (int)(lw[k] >> 16), lrow = (int)(lw[k] & 0xFFFFu);
         if (lr < wd) {
           band[lrow + lr] = make_float2(ev[k], lv[k]);
-          if (MODE == kSweep) e0l[lrow + lr] = ev[k];
+          if (MODE == kSweep && E0N == 0) e0l[lrow + lr] = ev[k];
         }
-        for (int c = lr + kRowLanes; c < wd; c += kRowLanes) {
-          const uint32_t gi = gs[k] + (uint32_t)c;
-          const float e2 = MODE == kSweep ? load_e(eag + gi) : 0.0f;
-          const float l2 = MODE != kRefresh ? lam[gi] : 0.0f;
-          band[lrow + c] = make_float2(e2, l2);
-          if (MODE == kSweep) e0l[lrow + c] = e2;
+        if constexpr (E0N == 0) {  // bands wider than 16 channels
+          for (int c = lr + kRowLanes; c < wd; c += kRowLanes) {
+            const uint32_t gi = gs[k] + (uint32_t)c;
+            const float e2 = MODE == kSweep ? load_e(eag + gi) : 0.0f;
+            const float l2 = MODE != kRefresh ? lam[gi] : 0.0f;
+            band[lrow + c] = make_float2(e2, l2);
+            if (MODE == kSweep) e0l[lrow + c] = e2;
+          }
         }
+      }
+    };
+    float e0r[E0N > 0 ? E0N : 1];
+    if constexpr (E0N > 0) {
+#pragma unroll
+      for (int kb = 0; kb < E0N; kb += kRowLanes) {
+        if (kb < a.kpad) {
+          float evb[kRowLanes];
+          stage_batch(kb, evb);
+#pragma unroll
+          for (int k = 0; k < kRowLanes; ++k) e0r[kb + k] = evb[k];
+        }
+      }
+    } else {
+      for (int kb = 0; kb < a.kpad; kb += kRowLanes) {
+        float evb[kRowLanes];
+        stage_batch(kb, evb);
       }
     }
     if (lr < 2) band[B + lr] = make_float2(0.0f, 0.0f);
@@ -314,19 +352,34 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
     // ---- 3. write back, 16 views at a time (entries broadcast as in the
     //         staging) ----
     if (MODE != kTheta2) {
-      for (int kb = 0; kb < a.kpad; kb += kRowLanes) {
+      auto flush_batch = [&](int kb, const float* e0b) {
         uint2 mine = make_uint2(0u, 0u);
         if (kb + lr < a.kpad) mine = *reinterpret_cast<const uint2*>(be + kb + lr);
 #pragma unroll
         for (int k = 0; k < kRowLanes; ++k) {
           const uint32_t g0 = row_bcast(mine.x, k), lw = row_bcast(mine.y, k);
           const int wd = (int)(lw >> 16), lrow = (int)(lw & 0xFFFFu);
-          for (int c = lr; c < wd; c += kRowLanes) {
-            float d = band[lrow + c].x;
-            if (MODE == kSweep) d -= e0l[lrow + c];
-            add_e(eag + g0 + c, d);
+          if constexpr (E0N > 0) {  // every band fits one chunk
+            if (lr < wd) {
+              float d = band[lrow + lr].x;
+              if (MODE == kSweep) d -= e0b[k];
+              add_e(eag + g0 + lr, d);
+            }
+          } else {
+            for (int c = lr; c < wd; c += kRowLanes) {
+              float d = band[lrow + c].x;
+              if (MODE == kSweep) d -= e0l[lrow + c];
+              add_e(eag + g0 + c, d);
+            }
           }
         }
+      };
+      if constexpr (E0N > 0) {
+#pragma unroll
+        for (int kb = 0; kb < E0N; kb += kRowLanes)
+          if (kb < a.kpad) flush_batch(kb, e0r + kb);
+      } else {
+        for (int kb = 0; kb < a.kpad; kb += kRowLanes) flush_batch(kb, nullptr);
       }
     }
     if (MODE == kSweep) {
@@ -372,30 +425,43 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
   }
 }
 
-template <int MODE, int SV, int NZL>
+template <int MODE, int SV, int NZL, int E0N>
 inline hipError_t launch_gen_mode(const SvArgs& a, int grid, size_t lds, hipStream_t st) {
   static std::atomic<bool> attr_set{false};
   if (!attr_set.load(std::memory_order_acquire)) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel_gen<MODE, SV, NZL>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&sv_kernel_gen<MODE, SV, NZL, E0N>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kMaxLdsBytes);
     if (e != hipSuccess) return e;
     attr_set.store(true, std::memory_order_release);
   }
-  hipLaunchKernelGGL((sv_kernel_gen<MODE, SV, NZL>), dim3(grid), dim3(a.rpb * kRowLanes), lds, st,
-                     a);
+  hipLaunchKernelGGL((sv_kernel_gen<MODE, SV, NZL, E0N>), dim3(grid), dim3(a.rpb * kRowLanes), lds,
+                     st, a);
   return hipGetLastError();
+}
+
+// The staged e in registers takes the smallest of 32, 48 and 64 slots that
+// holds kpad (only the sizes gen_e0_in_regs admits with these records).
+template <int SV, int NZL>
+inline hipError_t launch_gen_sweep(const SvArgs& a, int grid, size_t lds, hipStream_t st) {
+  if (!gen_e0_in_regs(a.kpad, a.wmax, a.nzp)) return launch_gen_mode<kSweep, SV, NZL, 0>(a, grid, lds, st);
+  if (a.kpad <= 2 * kRowLanes) return launch_gen_mode<kSweep, SV, NZL, 2 * kRowLanes>(a, grid, lds, st);
+  if constexpr (NZL != 16) {
+    if (a.kpad <= 3 * kRowLanes) return launch_gen_mode<kSweep, SV, NZL, 3 * kRowLanes>(a, grid, lds, st);
+  }
+  if constexpr (NZL == 0) return launch_gen_mode<kSweep, SV, NZL, 4 * kRowLanes>(a, grid, lds, st);
+  return hipErrorInvalidValue;  // not reached: gen_e0_in_regs bounds kpad
 }
 
 template <int SV>
 inline hipError_t launch_gen_s(const SvArgs& a, int mode, int grid, size_t lds, hipStream_t st) {
   if (mode == kSweep) {
-    if (a.nzp <= 8 * kRowLanes) return launch_gen_mode<kSweep, SV, 8>(a, grid, lds, st);
-    if (a.nzp <= 16 * kRowLanes) return launch_gen_mode<kSweep, SV, 16>(a, grid, lds, st);
-    return launch_gen_mode<kSweep, SV, 0>(a, grid, lds, st);
+    if (a.nzp <= 8 * kRowLanes) return launch_gen_sweep<SV, 8>(a, grid, lds, st);
+    if (a.nzp <= 16 * kRowLanes) return launch_gen_sweep<SV, 16>(a, grid, lds, st);
+    return launch_gen_sweep<SV, 0>(a, grid, lds, st);
   }
-  if (mode == kTheta2) return launch_gen_mode<kTheta2, SV, 0>(a, grid, lds, st);
-  return launch_gen_mode<kRefresh, SV, 0>(a, grid, lds, st);
+  if (mode == kTheta2) return launch_gen_mode<kTheta2, SV, 0, 0>(a, grid, lds, st);
+  return launch_gen_mode<kRefresh, SV, 0, 0>(a, grid, lds, st);
 }
 
 }  // namespace mace
