@@ -238,6 +238,9 @@ class System:
                  view_to_agent=None, precision=0, sv_size=0, rows_per_agent=0,
                  fp32_tail_iters=0, hbm_budget_bytes=0, refresh_every=0, format=0):
         self._h = None
+        # held by the object: at interpreter exit the module's globals may
+        # already be cleared when __del__ runs
+        self._free = _lib.mace_free_system
         cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
         rw = np.ascontiguousarray(row, dtype=np.int32)
         vl = np.ascontiguousarray(val, dtype=np.float32)
@@ -257,7 +260,7 @@ class System:
 
     def close(self):
         if self._h:
-            _lib.mace_free_system(self._h)
+            self._free(self._h)
             self._h = None
 
     def __del__(self):
@@ -464,6 +467,7 @@ class Server:
 
     def __init__(self, systems, hbm_budget_bytes=0):
         self._h = None
+        self._destroy = _lib.mace_server_destroy  # see System.__init__
         self.systems = list(systems)
         arr = (ctypes.c_void_p * len(self.systems))(*[s._h.value for s in self.systems])
         h = ctypes.c_void_p()
@@ -503,7 +507,7 @@ class Server:
 
     def close(self):
         if self._h:
-            _lib.mace_server_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     def __del__(self):
