@@ -44,6 +44,9 @@ __device__ __forceinline__ float dpp(float v) {
 
 // Sum over the 16 lanes of a DPP row; every lane receives the total.
 __device__ __forceinline__ float row_sum16(float v) {
+  // no contraction: each step stays one DPP add instead of an FMA that
+  // recomputes the caller's product beside a separate DPP move
+#pragma clang fp contract(off)
   v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp<0x141>(v);  // row_half_mirror
@@ -400,55 +403,63 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
     const size_t rec0 = (size_t)agent * a.n + pix0;
     // first LDS row of each of the lane's views in this task's band (the
     // dummy rows of the task for a view that misses the super-voxel)
-    int lrw[SL];
+    float2* bl[SL];
 #pragma unroll
-    for (int sl = 0; sl < SL; ++sl) lrw[sl] = cur.cb[sl].lds_row;
+    for (int sl = 0; sl < SL; ++sl) bl[sl] = band + cur.cb[sl].lds_row;
     auto update = [&](const Rec<SL>& cur, int j, int pi, int pj) {
       const int cidx = (pi + 1) * HS + pj + 1;
-      int o[SL];
+      // the pixel's two band rows in each of the lane's views
+      float2* o[SL];
 #pragma unroll
-      for (int s2 = 0; s2 < SL; ++s2) o[s2] = lrw[s2] + cur.off[s2];
+      for (int s2 = 0; s2 < SL; ++s2) o[s2] = bl[s2] + cur.off[s2];
       if (MODE == kSweep) {
         // every LDS read of this pixel first, then the arithmetic
         float2 p0[SL], p1[SL];
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2) {
-          p0[s2] = band[o[s2]];
-          p1[s2] = band[o[s2] + 1];
+          p0[s2] = o[s2][0];
+          p1[s2] = o[s2][1];
         }
         const float zs = halo[cidx];
         float nbv = halo[cidx + noff];
         const float vj = vv[j], tj = t2[j];
         // the neighbour lies in the image (lanes 8-15: weight 0 anyway)
         const int iy = y0 + pi + ndi8, ix = x0 + pj + ndj8;
-        float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+        // the clique's weight, 0 for a neighbour outside the image
+        float nbwin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? nbw : 0.0f;
         if constexpr (VOL) {
           if (axial) {
             nbv = cur.ax;
-            nin = ax_in;
+            nbwin = nbw * ax_in;
           }
         }
-        float part = 0.0f;
+        // the lane's share of theta1's sum: two FMA chains over the slots
+        // (first and second channel), joined at the end
+        float pa = cur.val[0].x * (p0[0].y * p0[0].x);
+        float pb = cur.val[0].y * (p1[0].y * p1[0].x);
 #pragma unroll
-        for (int s2 = 0; s2 < SL; ++s2)
-          part += cur.val[s2].x * p0[s2].y * p0[s2].x + cur.val[s2].y * p1[s2].y * p1[s2].x;
+        for (int s2 = 1; s2 < SL; ++s2) {
+          pa = __builtin_fmaf(cur.val[s2].x, p0[s2].y * p0[s2].x, pa);
+          pb = __builtin_fmaf(cur.val[s2].y, p1[s2].y * p1[s2].x, pb);
+        }
+        const float part = pa + pb;
         const float d = zs - nbv;
-        const float wgt = nbw * nin * prior_curv(a, d);
+        const float wgt = nbwin * prior_curv(a, d);
         const float gl = wgt * d + proxw * (zs - vj) - part;
-        const float G = row_sum16(gl);
         const float H = row_sum16(wgt);
+        const float G = row_sum16(gl);
         const float alpha = -a.relax * G * __builtin_amdgcn_rcpf(tj + H + a.is2);
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2) {
-          band[o[s2]].x = p0[s2].x - cur.val[s2].x * alpha;
-          band[o[s2] + 1].x = p1[s2].x - cur.val[s2].y * alpha;
+          o[s2][0].x = p0[s2].x - cur.val[s2].x * alpha;
+          o[s2][1].x = p1[s2].x - cur.val[s2].y * alpha;
         }
         if (lr == 0) halo[cidx] = zs + alpha;
       } else if (MODE == kTheta2) {
         float part = 0.0f;
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2) {
-          const float l0 = band[o[s2]].y, l1 = band[o[s2] + 1].y;
+          const float l0 = o[s2][0].y, l1 = o[s2][1].y;
           part += cur.val[s2].x * cur.val[s2].x * l0 + cur.val[s2].y * cur.val[s2].y * l1;
         }
         const float th = row_sum16(part);
@@ -460,8 +471,8 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
         const float xs = halo[cidx];
 #pragma unroll
         for (int s2 = 0; s2 < SL; ++s2) {
-          band[o[s2]].x -= cur.val[s2].x * xs;
-          band[o[s2] + 1].x -= cur.val[s2].y * xs;
+          o[s2][0].x -= cur.val[s2].x * xs;
+          o[s2][1].x -= cur.val[s2].y * xs;
         }
       }
       __builtin_amdgcn_wave_barrier();

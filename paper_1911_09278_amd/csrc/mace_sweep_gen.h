@@ -273,13 +273,14 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
       float nbv = halo[cidx + noff];
       const float vj = vv[j], tj = t2[j];
       const int iy = y0 + pi + ndi8, ix = x0 + pj + ndj8;
-      float nin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? 1.0f : 0.0f;
+      // the clique's weight, 0 for a neighbour outside the image (volume)
+      float nbwin = ((unsigned)iy < (unsigned)a.ny && (unsigned)ix < (unsigned)a.nx) ? nbw : 0.0f;
       if (axial) {
         nbv = lr == 9 ? xlo[j] : xhi[j];
-        nin = (lr == 9 ? has_lo : has_hi) ? 1.0f : 0.0f;
+        nbwin = (lr == 9 ? has_lo : has_hi) ? nbw : 0.0f;
       }
       const float d = zs - nbv;
-      const float wgt = nbw * nin * prior_curv(a, d);
+      const float wgt = nbwin * prior_curv(a, d);
       const float gl = wgt * d + proxw * (zs - vj) - part;
       const float G = row_sum16(gl);
       const float H = row_sum16(wgt);
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
             for (int u = 0; u < NZL; ++u)
               if (u < nu) {
                 const float2 p = band[r.row[u]];
-                part += r.val[u] * p.y * p.x;
+                part = __builtin_fmaf(r.val[u], p.y * p.x, part);
               }
             const float alpha = step_alpha(j, part);
             // the rows of one column are distinct; padding entries add 0 to
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
           float part = 0.0f;
           for (int u = 0; u < nu; ++u) {
             const float2 p = band[gr[u * kRowLanes]];
-            part += gv[u * kRowLanes] * p.y * p.x;
+            part = __builtin_fmaf(gv[u * kRowLanes], p.y * p.x, part);
           }
           const float alpha = step_alpha(j, part);
           for (int u = 0; u < nu; ++u) band[gr[u * kRowLanes]].x -= gv[u * kRowLanes] * alpha;
