@@ -125,3 +125,53 @@ def test_general_records_match_compact_records(m):
         sysm.close()
     scale = np.abs(xs[1]).max()
     assert np.abs(xs[1] - xs[2]).max() <= 5e-5 * scale
+
+
+def _dense_columns(nx, ny, n_views, n_ch, seed):
+    """A synthetic CSC matrix whose every column has a nonzero in every
+    channel of every view (values in [0.05, 0.35)), with Poisson data from
+    a random image: far more nonzeros per view than a ray geometry gives,
+    on bands of only n_ch channels."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n, rows = nx * ny, n_views * n_ch
+    cp = np.arange(n + 1, dtype=np.int64) * rows
+    row = np.tile(np.arange(rows, dtype=np.int32), n)
+    val = rng.uniform(0.05, 0.35, size=n * rows).astype(np.float32)
+    x_true = rng.uniform(0.0, 0.04, size=n)
+    A = np.zeros((rows, n))
+    A[row, np.repeat(np.arange(n), rows)] = val.astype(np.float64)
+    counts = np.maximum(rng.poisson(1e4 * np.exp(-(A @ x_true))), 1).astype(np.float64)
+    y = (-np.log(counts / 1e4)).astype(np.float32)
+    return (cp, row, val), y, counts.astype(np.float32)
+
+
+DENSE_CASES = [
+    # views, channels, agents: records per (agent, pixel), view slots
+    (60, 6, 1),   # 360 entries (read in the pixel loop), 64 slots: staged e in 64 registers
+    (45, 6, 1),   # 270 entries, 48 slots: 48 registers
+    (60, 6, 2),   # 180 entries (16 per lane in registers), 32 slots: 32 registers
+    (45, 4, 1),   # 180 entries, 48 slots: too many beside 16 record registers, e in LDS
+]
+
+
+@pytest.mark.parametrize("case", DENSE_CASES, ids=lambda c: f"v{c[0]}c{c[1]}_N{c[2]}")
+def test_general_dense_columns_trajectory_matches_oracle(m, case):
+    """Columns with many nonzeros per view and narrow bands: the staged-e
+    register variants for long records, against the oracle's trajectory."""
+    nv, nc, N = case
+    nx = ny = 8
+    (cp, row, val), y, lam = _dense_columns(nx, ny, nv, nc, 500 + nv + nc + N)
+    va = mi.interleaved_partition(nv, N)
+    O = oracle.Oracle(nx, ny, nv, nc, cp, row, val, y, lam, va, 1, 0.002, 2.0, 1.2, 1.0)
+    print(f"dense columns {nx}x{ny}, {nv} views x {nc} channels, N={N}", flush=True)
+    sysm = m.System(nx, ny, nv, nc, cp, row, val, N, sv_size=4, rows_per_agent=1, format=2)
+    assert sysm.config["format"] == 2
+    prior = m.make_prior(1, 0.002, 2.0, 1.2, 1.0)
+    x, info = sysm.solve(y, lam, prior, 0.8, 0.002, 4)
+    w, X = sysm.state()
+    ref = O.mace_solve(0.8, 0.002, 4, order=sysm.visit_order(), mode=oracle.MODE_SURROGATE)
+    scale = np.abs(ref["x"]).max()
+    assert np.all(np.isfinite(x))
+    assert np.abs(X - ref["X"]).max() <= 5e-5 * scale, np.abs(X - ref["X"]).max() / scale
+    assert np.abs(x - ref["x"]).max() <= 5e-5 * scale
+    assert abs(info.residual - ref["resid"][-1]) <= 1e-3 * ref["resid"][-1] + 1e-7
