@@ -166,6 +166,9 @@ class Oracle:
         inp = _In(self.nx, self.ny, self.n_views, self.n_ch, _p(cp), _p(rw), _p(vl), _p(yy),
                   _p(ll), self.N, _p(va), int(prior_kind), float(sigma_x), float(p), float(q),
                   float(T), float(b_edge), float(b_diag), self.nz, float(b_axial))
+        # held by the object: at interpreter exit the module's globals may
+        # already be cleared when __del__ runs
+        self._destroy = L.orc_destroy
         self._h = L.orc_create(ctypes.byref(inp))
         if not self._h:
             raise ValueError("oracle: bad problem description")
@@ -175,7 +178,7 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _load().orc_destroy(h)
+            self._destroy(h)
             self._h = None
 
     def set_data(self, y, lam):
