@@ -155,3 +155,55 @@ def test_volume_argument_errors(m):
     assert ei.value.code == m.MACE_E_ARG
     with pytest.raises(ValueError):
         general.solve_volume(y[:, :-1], lam[:, :-1], prior, 0.5, 0.8, 0.001, 2)
+
+
+@pytest.mark.parametrize("fmt", [2, 1])
+def test_volume_of_one_slice_is_the_2d_solve(m, fmt):
+    """nz = 1: no axial neighbour exists, so the volume is the slice's own
+    2-D problem, whatever b_axial says."""
+    g = mi.Geometry(24, 24, 24, 36)
+    (cp, row, val), y, lam, _ = _volume(g, 1, 63, 2, 1, 0.002, 0.5, 1.2)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2, sv_size=8,
+                    rows_per_agent=1, format=fmt)
+    prior = m.make_prior(1, 0.002, 2.0, 1.2, 1.0)
+    xv, iv = sysm.solve_volume(y, lam, prior, 0.5, 0.8, 0.001, 5)
+    xs, i2 = sysm.solve(y[0], lam[0], prior, 0.8, 0.001, 5)
+    assert np.abs(xv[0] - xs).max() <= 1e-6 * np.abs(xs).max()
+    assert abs(iv.residual - i2.residual) <= 1e-5 * i2.residual
+
+
+def test_volume_of_128_slices_matches_oracle(m):
+    """The largest volume (128 slices, every scan slot), sequential schedule:
+    the trajectory equals the oracle's 3-D one in the GPU's visiting order."""
+    g = mi.Geometry(16, 16, 8, 24)
+    nz, N, S, iters = 128, 2, 8, 2
+    (cp, row, val), y, lam, O = _volume(g, nz, 900, N, 0, 0.003, 0.5)
+    print(f"volume of {nz} slices {g}", flush=True)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=S,
+                    rows_per_agent=1, format=1)
+    prior = m.make_prior(0, 0.003)
+    x, info = sysm.solve_volume(y, lam, prior, 0.5, 0.8, 0.002, iters)
+    order = _volume_order(sysm, g, nz, S)
+    ref = O.mace_solve(0.8, 0.002, iters, order=order, mode=oracle.MODE_SURROGATE)
+    scale = np.abs(ref["x"]).max()
+    assert np.abs(x.reshape(-1) - ref["x"]).max() <= 5e-5 * scale
+    assert abs(info.residual - ref["resid"][-1]) <= 1e-3 * ref["resid"][-1] + 1e-7
+
+
+def test_volume_slice_count_out_of_range(m):
+    """nz outside [1, 128] is an argument error at the C ABI, raised before
+    any input is read."""
+    import ctypes
+    g = mi.Geometry(16, 16, 8, 24)
+    cp, row, val = mi.system_matrix(g)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2)
+    prior = m.make_prior(0, 0.003)
+    y = np.zeros(g.n_rows, dtype=np.float32)
+    x = np.zeros(g.n, dtype=np.float32)
+    info = m.Info()
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    for nz in (0, -1, 129):
+        rc = m._lib.mace_solve_volume(sysm._h, nz, p(y), p(y), ctypes.byref(prior), 0.5, 0.8,
+                                      0.002, 1, 2, 0.0, p(x), ctypes.byref(info))
+        assert rc == m.MACE_E_ARG, (nz, rc)
+        assert "nz must be in [1, 128]" in m.last_error()
