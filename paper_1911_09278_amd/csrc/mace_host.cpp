@@ -565,10 +565,11 @@ static int check_pack(const mace_system* s, const HostPack& hp) {
 // scratch would not fit 16 to the 160 KiB of LDS (many views per agent).
 static int pick_rows_per_block(mace_system* s) {
   s->rpb = sv_rows_per_block(s->bmax, s->S, s->kpad, s->format, s->wmax, s->nzp);
-  if (s->rpb == 0)
+  if (s->rpb == 0)  // rows of 16 lanes: at least 4 per workgroup (compact), 1 (general)
     return fail(MACE_E_ARG,
-                "a super-voxel band of %d rows needs more than 40 KiB of LDS per row; %s", s->bmax,
-                s->S > 4 ? "use sv_size 4" : "use more agents (fewer views per agent)");
+                "a super-voxel band of %d rows needs more than %d KiB of LDS per row; %s", s->bmax,
+                (int)(kMaxLdsBytes / 1024 / (s->format == 1 ? 1 : 4)),
+                s->S > 4 ? "use a smaller sv_size" : "use more agents (fewer views per agent)");
   return MACE_OK;
 }
 

@@ -141,6 +141,22 @@ def test_general_layout_indices_in_bounds(case):
     assert 0 < lds <= 160 * 1024
 
 
+def test_general_band_too_large_for_lds():
+    """One agent with all 720 views of a 32x32 image: 8x8 super-voxels fit
+    one row of 16 lanes per workgroup (89 KB); 16x16 ones need more than a
+    CU's 160 KiB for one row and are refused with the size and the fix."""
+    import paper_1911_09278_amd as m
+    g = mi.Geometry(32, 32, 720, 48)
+    cp, row, val = mi.system_matrix(g)
+    lds = m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 1, sv_size=8,
+                         format=2)
+    assert 80 * 1024 < lds <= 160 * 1024
+    with pytest.raises(m.MaceError) as e:
+        m.check_layout(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 1, sv_size=16, format=2)
+    assert e.value.code == m.MACE_E_ARG
+    assert "more than 160 KiB of LDS per row" in str(e.value) and "smaller sv_size" in str(e.value)
+
+
 LAYOUT_CASES = [
     (mi.Geometry(32, 32, 64, 48), 4, 4), (mi.Geometry(42, 38, 180, 64), 4, 4),
     (mi.Geometry(24, 24, 100, 40), 2, 8), (mi.Geometry(20, 20, 30, 32), 1, 4),
