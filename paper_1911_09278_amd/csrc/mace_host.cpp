@@ -181,7 +181,8 @@ static int repack_general(mace_system* s, const int64_t* cp, const int32_t* row,
                           HostPack& hp) {
   const int N = s->N, n = s->n, kpad = s->kpad, S = s->S;
   sv_tiling(s);
-  // entries per (agent, column); nzp = the largest, rounded up to 16
+  // entries per (agent, column); nzp = the largest, rounded up to 32 (the
+  // sweep's lanes take the entries in pairs, 16 lanes)
   int maxc = 0;
   {
     std::vector<int> cnt(N);
@@ -191,7 +192,8 @@ static int repack_general(mace_system* s, const int64_t* cp, const int32_t* row,
       for (int a = 0; a < N; ++a) maxc = std::max(maxc, cnt[a]);
     }
   }
-  s->nzp = std::max(kRowLanes, (maxc + kRowLanes - 1) / kRowLanes * kRowLanes);
+  const int pair_row = 2 * kRowLanes;
+  s->nzp = std::max(pair_row, (maxc + pair_row - 1) / pair_row * pair_row);
   const size_t nrec = (size_t)N * n;
   hp.gval.assign(nrec * s->nzp, 0.0f);
   hp.grow.assign(nrec * s->nzp, 0);

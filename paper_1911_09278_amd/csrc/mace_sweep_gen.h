@@ -8,12 +8,14 @@
 // the reflection + Mann update with FP64 residual partials.  What differs:
 //   * a record is the list of the pixel's nonzeros in the agent's rows, as
 //     (LDS row of the band, value) pairs padded to nzp entries (a multiple
-//     of 16) with zero values on the task's dummy row; a column may have any
+//     of 32) with zero values on the task's dummy row; a column may have any
 //     number of nonzeros per view, on any channels;
 //   * a view's band may be wider than 16 channels, and an agent may own any
 //     number of views: the band is staged and written back view by view in
 //     chunks of 16 channels;
-//   * the staged copy of e that the write-back subtracts lives in LDS;
+//   * the staged copy of e that the write-back subtracts lives in
+//     registers when every band fits 16 channels and the view slots fit
+//     beside the record registers, else in LDS;
 //   * super-voxel sides 4, 8, 16 and 32;
 //   * volumes: slice z of a stack lives in slot z, and lanes 9 and 10 add
 //     the axial cliques to the voxels of slices z - 1 and z + 1 of the same
@@ -21,8 +23,8 @@
 //     sweep in separate launches, so the axial neighbours a task stages do
 //     not change while it runs.
 // Records of up to 256 entries (the common case: 1 mm channels and tens of
-// views per agent) are held in registers in the sweep, loaded two pixels
-// ahead; longer ones are read in the pixel loop.  Loops over views and
+// views per agent) are held in registers in the sweep, two entries per load,
+// loaded two pixels ahead; longer ones are read in the pixel loop.  Loops over views and
 // pixels are not unrolled.  FP32 values only.
 #include <hip/hip_runtime.h>
 
@@ -81,26 +83,28 @@ __device__ __forceinline__ uint32_t row_bcast(uint32_t v, int l) {
   }
 }
 
-// The lane's share of a general record: entries lr, lr + 16, ... of the
-// pixel's list, nzp / 16 <= NZL of them (the list's own padding holds 0 on
-// the task's dummy row).
+// The lane's share of a general record in the register path: entry pairs
+// (2p, 2p + 1) for p = lr, lr + 16, ..., nzp / 32 <= NZL / 2 of them, each
+// pair one 8-byte value load and one 4-byte load of its two 16-bit rows
+// (the list's own padding holds 0 on the task's dummy row).
 template <int NZL>
 struct GenRec {
-  float val[NZL];
-  int row[NZL];
+  float2 val[NZL / 2];
+  uint32_t row2[NZL / 2];  // rows of the pair: low and high 16 bits
 };
 
 template <int NZL>
 __device__ __forceinline__ void load_gen(const SvArgs& a, size_t rec0, int j, int lr,
                                          GenRec<NZL>& g) {
-  const float* gv = a.gval + (rec0 + j) * (size_t)a.nzp + lr;
-  const uint16_t* gr = a.grow + (rec0 + j) * (size_t)a.nzp + lr;
-  const int nu = a.nzp / kRowLanes;  // the same for every lane: nzp is a multiple of 16
+  const size_t base = (rec0 + j) * (size_t)a.nzp;  // even: nzp is a multiple of 32
+  const float2* gv = reinterpret_cast<const float2*>(a.gval + base) + lr;
+  const uint32_t* gr = reinterpret_cast<const uint32_t*>(a.grow + base) + lr;
+  const int np = a.nzp / (2 * kRowLanes);  // pairs per lane, the same for every lane
 #pragma unroll
-  for (int u = 0; u < NZL; ++u)
-    if (u < nu) {  // slots past nu are never read
+  for (int u = 0; u < NZL / 2; ++u)
+    if (u < np) {  // slots past np are never read
       g.val[u] = gv[u * kRowLanes];
-      g.row[u] = gr[u * kRowLanes];
+      g.row2[u] = gr[u * kRowLanes];
     }
 }
 
@@ -288,8 +292,10 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
       if (lr == 0) halo[cidx] = zs + alpha;
       return alpha;
     };
-    // entries per lane: nzp is a multiple of 16, the same for every lane
+    // entries per lane, and entry pairs per lane in the register path: nzp
+    // is a multiple of 32, the same for every lane
     const int nu = a.nzp / kRowLanes;
+    const int np = a.nzp / (2 * kRowLanes);
     if constexpr (MODE == kSweep && NZL > 0) {
       // records of at most 16 NZL entries: the lane's share in registers,
       // loaded two pixels ahead
@@ -303,19 +309,23 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
           if (j < npix) {
             if (j + 2 < npix) load_gen<NZL>(a, rec0, j + 2, lr, buf[(q + 2) % 3]);
             const GenRec<NZL>& r = buf[q];
-            float part = 0.0f;
+            float pa = 0.0f, pb = 0.0f;  // first and second entries of the pairs
 #pragma unroll
-            for (int u = 0; u < NZL; ++u)
-              if (u < nu) {
-                const float2 p = band[r.row[u]];
-                part = __builtin_fmaf(r.val[u], p.y * p.x, part);
+            for (int u = 0; u < NZL / 2; ++u)
+              if (u < np) {
+                const float2 p0 = band[r.row2[u] & 0xFFFFu], p1 = band[r.row2[u] >> 16];
+                pa = __builtin_fmaf(r.val[u].x, p0.y * p0.x, pa);
+                pb = __builtin_fmaf(r.val[u].y, p1.y * p1.x, pb);
               }
-            const float alpha = step_alpha(j, part);
+            const float alpha = step_alpha(j, pa + pb);
             // the rows of one column are distinct; padding entries add 0 to
             // the dummy row
 #pragma unroll
-            for (int u = 0; u < NZL; ++u)
-              if (u < nu) band[r.row[u]].x -= r.val[u] * alpha;
+            for (int u = 0; u < NZL / 2; ++u)
+              if (u < np) {
+                band[r.row2[u] & 0xFFFFu].x -= r.val[u].x * alpha;
+                band[r.row2[u] >> 16].x -= r.val[u].y * alpha;
+              }
             __builtin_amdgcn_wave_barrier();
           }
         }
