@@ -310,21 +310,25 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
             if (j + 2 < npix) load_gen<NZL>(a, rec0, j + 2, lr, buf[(q + 2) % 3]);
             const GenRec<NZL>& r = buf[q];
             float pa = 0.0f, pb = 0.0f;  // first and second entries of the pairs
+            float ea[NZL / 2], eb[NZL / 2];  // their e, kept for the update
 #pragma unroll
             for (int u = 0; u < NZL / 2; ++u)
               if (u < np) {
                 const float2 p0 = band[r.row2[u] & 0xFFFFu], p1 = band[r.row2[u] >> 16];
+                ea[u] = p0.x;
+                eb[u] = p1.x;
                 pa = __builtin_fmaf(r.val[u].x, p0.y * p0.x, pa);
                 pb = __builtin_fmaf(r.val[u].y, p1.y * p1.x, pb);
               }
             const float alpha = step_alpha(j, pa + pb);
-            // the rows of one column are distinct; padding entries add 0 to
-            // the dummy row
+            // the rows of one column are distinct, so no other lane changes
+            // them meanwhile; padding entries write back the dummy row's
+            // value unchanged
 #pragma unroll
             for (int u = 0; u < NZL / 2; ++u)
               if (u < np) {
-                band[r.row2[u] & 0xFFFFu].x -= r.val[u].x * alpha;
-                band[r.row2[u] >> 16].x -= r.val[u].y * alpha;
+                band[r.row2[u] & 0xFFFFu].x = ea[u] - r.val[u].x * alpha;
+                band[r.row2[u] >> 16].x = eb[u] - r.val[u].y * alpha;
               }
             __builtin_amdgcn_wave_barrier();
           }
