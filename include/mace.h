@@ -15,10 +15,12 @@
  * Conventions
  *   - Image: nx * ny pixels, raster order s = i * nx + j (row i, column j).
  *   - Sinogram rows: r = view * n_channels + channel (view-major).
- *   - A is given in compressed sparse columns (one column per pixel).  Within
- *     one view a column may have at most two nonzeros, on adjacent channels
- *     (true whenever the channel spacing is at least the pixel width over
- *     sqrt(2), e.g. 1 mm pixels and 1 mm channels).
+ *   - A is given in compressed sparse columns (one column per pixel), with
+ *     any sparsity pattern.  Columns with at most two nonzeros per view, on
+ *     adjacent channels (true whenever the channel spacing is at least the
+ *     pixel width over sqrt(2), e.g. 1 mm pixels and 1 mm channels), and at
+ *     most 128 views per agent fit the compact device records; any other
+ *     matrix takes the general records (mace_opts.format).
  *   - Units are the caller's (e.g. A in mm, x in 1/mm).
  *   - Every int-returning call returns MACE_OK (0), a negative error code, or
  *     a positive warning; mace_last_error() describes the last failure of the
@@ -134,12 +136,14 @@ typedef struct {
  *   row_idx[nnz] (ascending and distinct within a column, < n_views*n_channels),
  *   val[nnz] (finite).
  *   view_to_agent[n_views]: agent of each view (NULL = interleaved, view k ->
- *   agent k mod n_agents); every agent must own at least one view and at most
- *   128 views.
+ *   agent k mod n_agents); every agent must own at least one view (more than
+ *   128 views per agent take the general records).
  * The matrix is copied and repacked on the device; *out receives the handle.
  * A super-voxel's band (its channels in every view of the agent) is staged in
- * LDS: workgroups hold 16 rows, or 8 or 4 when a band is too large for 16
- * (many views per agent); MACE_E_ARG if even 4 rows do not fit 160 KiB.
+ * LDS, one row of 16 lanes per (agent, super-voxel) task: workgroups hold 16,
+ * 8 or 4 rows, whichever keeps the most rows of a CU's 160 KiB resident (the
+ * general records go down to 2 or 1); MACE_E_ARG if even the smallest
+ * workgroup does not fit 160 KiB (a smaller sv_size or more agents help).
  * Errors: MACE_E_ARG, MACE_E_MATRIX, MACE_E_PARTITION, MACE_E_NOMEM, MACE_E_HIP.
  */
 int mace_load_system(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
