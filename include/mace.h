@@ -400,8 +400,9 @@ int mace_autotune(const mace_geom* geom, const int64_t* col_ptr, const int32_t* 
  * device tables and the super-voxel schedules in host memory and checks every
  * index the kernels form from them (band rows, record rows, task ids, LDS
  * size), without using a device.  *lds_bytes (optional) receives the LDS a
- * workgroup of the main kernel needs (for the rows per workgroup chosen: 16,
- * 8 or 4).  Same error codes as mace_load_system.
+ * workgroup of the main kernel needs in a 2-D solve (for the rows per
+ * workgroup chosen: 16, 8 or 4; 2 or 1 for general records with very wide
+ * bands).  Same error codes as mace_load_system.
  */
 int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr, const int32_t* row_idx,
                       const float* val, int32_t n_agents, const int32_t* view_to_agent,
