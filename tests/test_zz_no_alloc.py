@@ -5,7 +5,8 @@ With the sequential schedule (one super-voxel of an agent at a time) both
 entry points are deterministic and run the same kernels with the same
 arguments, so the images, residuals and iteration counts must be identical.
 Two calls in a row, the second on a smaller system, check that the static
-workspace carries nothing from one call to the next; a concurrent-schedule
+workspace carries nothing from one call to the next (compact and general
+record formats); a concurrent-schedule
 case checks the fixed point to the FP32 tolerance; a system whose scan state
 exceeds the workspace is refused before any launch.
 """
@@ -57,6 +58,28 @@ def test_noalloc_equals_solve_dev_twice_second_smaller(m):
         assert np.all(np.isfinite(xb))
         assert np.array_equal(xa, xb), np.abs(xa - xb).max()
         assert ia.iters == ib.iters == 9 and ia.residual == ib.residual
+        sysm.close()
+
+
+def test_noalloc_general_records_equal_solve_dev(m):
+    """The general record format (0.4 mm channels: several nonzeros of a
+    column per view) through both entry points, sequential schedule: the
+    same image, residual and iteration count, on two calls in a row, the
+    second smaller."""
+    prior = m.make_prior(1, 0.002, 2.0, 1.2, 1.0)
+    cases = [(mi.Geometry(32, 32, 48, 113, pix=1.0, chan=0.4), 2, 41),
+             (mi.Geometry(24, 24, 30, 64, pix=1.0, chan=0.4), 2, 42)]
+    for g, N, seed in cases:
+        print("general records", g, "N", N, flush=True)
+        cp, row, val = mi.system_matrix(g)
+        s = mi.scan(g, seed)
+        sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, rows_per_agent=1,
+                        format=2)
+        assert sysm.config["format"] == 2
+        xa, ia, xb, ib = _both(m, sysm, s, prior, 0.002, 6)
+        assert np.all(np.isfinite(xb))
+        assert np.array_equal(xa, xb), np.abs(xa - xb).max()
+        assert ia.iters == ib.iters == 6 and ia.residual == ib.residual
         sysm.close()
 
 
