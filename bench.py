@@ -110,6 +110,55 @@ def host_info():
     return {"cpu_model": model, "ram_bytes": ram, "host_threads": os.cpu_count()}
 
 
+def bench_oracle(mi):
+    """The FP64 oracle timed per Mann iteration on the 64^2 (4 agents), 512^2
+    (16 agents) and 1024^2 (32 agents) workloads: the median over repeats of
+    (time of 1 + K iterations - time of 1 iteration) / K, so that the set-up
+    of a solve (theta2, e = y) drops out, with K sized for about 2 s (at most
+    200).  The 64 batched 512^2 slices are the
+    512^2 iteration times 64 (the oracle solves each slice alone), labelled
+    as extrapolated.  Host only; no GPU is used."""
+    import statistics
+    import oracle
+    res = {}
+    for cfg, name, sigma, reps in (("config1", "plain64", 1e-3, 5), ("config2", "scan512", 1e-4, 5),
+                                   ("config4", "scan1024", 5e-5, 3)):
+        w = mi.WORKLOADS[name]
+        g = w.geom
+        log(f"oracle: {name}")
+        cp, row, val = mi.system_matrix(g)
+        sc = mi.scan(g, w.seed)
+        va = mi.interleaved_partition(g.n_views, w.n_agents)
+        O = oracle.Oracle(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, sc.y, sc.lam, va,
+                          w.prior_kind, w.sigma_x, w.p, w.q, w.T)
+        nnz = int(cp[-1])
+        del cp, row, val
+        t0 = time.perf_counter()
+        O.mace_solve(w.rho, sigma, 2)
+        t2 = time.perf_counter() - t0
+        K = max(2, min(200, int(2.0 / max(t2 / 2.0, 1e-4))))
+        per = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            O.mace_solve(w.rho, sigma, 1)
+            t1 = time.perf_counter()
+            O.mace_solve(w.rho, sigma, 1 + K)
+            tk = time.perf_counter()
+            per.append(((tk - t1) - (t1 - t0)) / K)
+        del O
+        med = statistics.median(per)
+        res[cfg] = {"workload": f"{name}: {g.nx}x{g.ny}, {g.n_views} views, {g.n_channels} "
+                                f"channels, {w.n_agents} agents, nnz {nnz}",
+                    "sigma": sigma, "repeats": reps, "iterations_per_sample": K,
+                    "ms_per_mann_iter": med * 1e3,
+                    "voxel_updates_per_s": w.n_agents * g.n / med}
+    res["config3_extrapolated"] = {
+        "workload": "64 slices of 512x512 (each solved alone by the oracle)",
+        "ms_per_mann_iter": 64 * res["config2"]["ms_per_mann_iter"],
+        "note": "extrapolated: 64 x the 512x512 iteration"}
+    return {"oracle": res, "cores": oracle.num_threads(), **host_info()}
+
+
 def leg_slices(sysm, w8, m, mi, torch, sigma, iters, n_slices=64):
     """Batched slices (64 independent 512x512 slices, each its own phantom,
     sharing the loaded scan512 system): all slices advance together through
@@ -830,14 +879,15 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--mode", default="scan",
-                    choices=("scan", "slices", "serve", "fp16", "pnp", "study", "volume"),
+                    choices=("scan", "slices", "serve", "fp16", "pnp", "study", "volume", "oracle"),
                     help="scan: the headline one-scan benchmark (default); slices: 64 "
                          "512x512 slices sharing one matrix, batched vs one at a time; "
                          "serve: Poisson arrivals of mixed-size scans through the server; "
                          "fp16: 1024x1024 FP16 matrix values vs FP32; "
                          "pnp: MACE-PnP with the binomial stand-in denoiser; "
                          "study: equits to convergence vs rho and vs the number of agents; "
-                         "volume: 16 coupled 256x256 slices vs the same slices as a batch")
+                         "volume: 16 coupled 256x256 slices vs the same slices as a batch; "
+                         "oracle: the FP64 oracle's time per Mann iteration on this host")
     ap.add_argument("--scans", type=int, default=30, help="serve: number of arrivals")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
     ap.add_argument("--slices", type=int, default=64, help="slices: batch size")
@@ -864,6 +914,9 @@ def main():
                           "launches": 3}))
         return
     import mace_inputs as mi
+    if args.mode == "oracle":
+        print(json.dumps(bench_oracle(mi)), flush=True)
+        return
     from __graft_entry__ import _ensure_built
     _ensure_built()
     import paper_1911_09278_amd as m
