@@ -110,6 +110,25 @@ def host_info():
     return {"cpu_model": model, "ram_bytes": ram, "host_threads": os.cpu_count()}
 
 
+def copy_bandwidth_gbs(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (read + write) timed with events: the
+    HBM bandwidth a plain streaming kernel reaches on this GPU."""
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def bench_oracle(mi):
     """The FP64 oracle timed per Mann iteration on the 64^2 (4 agents), 512^2
     (16 agents) and 1024^2 (32 agents) workloads: the median over repeats of
@@ -1013,6 +1032,10 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6,
                      "bytes_per_launch": bytes_launch},
     }
+    # the same bandwidth against what a plain 1 GiB device copy reaches
+    copy_gbs = copy_bandwidth_gbs(torch)
+    out["roofline"]["copy_gbs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = achieved / copy_gbs
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, cp, row, val, scan, va, w8, args.sigma)
