@@ -23,9 +23,10 @@
 //     sweep in separate launches, so the axial neighbours a task stages do
 //     not change while it runs.
 // Records of up to 256 entries (the common case: 1 mm channels and tens of
-// views per agent) are held in registers in the sweep, two entries per load,
-// loaded two pixels ahead; longer ones are read in the pixel loop.  Loops over views and
-// pixels are not unrolled.  FP32 values only.
+// views per agent) are held in registers in the sweep, two entries per
+// load, loaded two pixels ahead; longer ones are read in the pixel loop.
+// The pixel loop is not unrolled, nor the loops over views unless the
+// staged e is in registers.  FP32 values only.
 #include <hip/hip_runtime.h>
 
 #include "mace_internal.h"
