@@ -161,6 +161,8 @@ int mace_load_system(const mace_geom* geom, const int64_t* col_ptr, const int32_
  * Returns MACE_OK, MACE_W_MAXITER (tol > 0 not reached), MACE_E_NONFINITE
  * (the iteration diverged: its state or residual is not finite, with or
  * without tol; x_out then holds non-finite values), or another error.
+ * max_iters = 0 runs no iteration: x_out = mean_i w_init (0 without it),
+ * info->iters = 0 and residual 0, and MACE_W_MAXITER if tol > 0.
  */
 int mace_solve(mace_system* sys, const float* y, const float* lambda, const mace_prior* prior,
                double rho, double sigma, int32_t sweeps, int32_t max_iters, double tol,

@@ -261,7 +261,8 @@ extern "C" int mace_solve_dev_noalloc(mace_system* s, const float* y, const floa
   HIP_OK(hipMemcpyAsync(&last, L.lastres, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   if (status == MACE_OK && !std::isfinite(last)) status = MACE_E_NONFINITE;
-  if (status == MACE_OK && tol > 0 && !(last < tol)) status = MACE_W_MAXITER;
+  // no iteration run (max_iters = 0): tol is not met
+  if (status == MACE_OK && tol > 0 && (k == 0 || !(last < tol))) status = MACE_W_MAXITER;
   if (info) {
     *info = mace_info{};
     info->iters = k;

@@ -451,7 +451,9 @@ int solve_batch_impl(mace_system* s, int n, const BatchIO* io, const mace_prior*
     // x = mean_i w_i: wbar holds it after the scan's last epilogue
     HIP_OK(hipMemcpyAsync(io[i].x_out, q.wbar.p, sizeof(float) * s->n, hipMemcpyDeviceToDevice, st));
     if (status[i] == MACE_OK && !std::isfinite(last[i])) status[i] = MACE_E_NONFINITE;
-    if (status[i] == MACE_OK && tol > 0 && !(last[i] < tol)) status[i] = MACE_W_MAXITER;
+    // no iteration run (max_iters = 0): tol is not met
+    if (status[i] == MACE_OK && tol > 0 && (iters[i] == 0 || !(last[i] < tol)))
+      status[i] = MACE_W_MAXITER;
     if (io[i].info) {
       io[i].info->iters = iters[i];
       io[i].info->residual = last[i];
@@ -576,7 +578,7 @@ int solve_volume_impl(mace_system* s, int nz, const float* y, const float* lam,
                           hipMemcpyDeviceToDevice, st));
   }
   HIP_OK(hipStreamSynchronize(st));
-  if (status == MACE_OK && tol > 0 && !(r < tol)) status = MACE_W_MAXITER;
+  if (status == MACE_OK && tol > 0 && (it == 0 || !(r < tol))) status = MACE_W_MAXITER;
   if (info) {
     *info = mace_info{};
     info->iters = it;

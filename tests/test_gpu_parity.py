@@ -340,3 +340,27 @@ def test_diverging_iteration_is_reported_not_converged(m):
         assert e.value.code == m.MACE_E_NONFINITE, (tol, e.value)
     x, info = sysm.solve(s.y, s.lam, prior, w8.rho, 1e-4, 5)
     assert np.all(np.isfinite(x)) and np.isfinite(info.residual) and info.residual > 0
+
+
+def test_zero_iterations_return_the_initial_consensus(m):
+    """max_iters = 0 runs no Mann iteration: x = mean_i w_init (0 without a
+    warm start), no iteration counted, and a tolerance cannot have been met
+    (MACE_W_MAXITER), for one scan and for a volume."""
+    g = mi.Geometry(32, 32, 64, 48)
+    N = 4
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, 7)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N)
+    prior = m.make_prior(0, 0.002)
+    w0 = np.random.default_rng(3).uniform(0.0, 0.03, N * g.n).astype(np.float32)
+    x, info = sysm.solve(s.y, s.lam, prior, 0.8, 1e-3, 0, w_init=w0)
+    mean = w0.reshape(N, g.n).astype(np.float64).mean(axis=0)
+    assert info.iters == 0 and info.status == m.MACE_OK
+    assert np.abs(x - mean).max() <= 1e-6 * np.abs(mean).max()
+    x, info = sysm.solve(s.y, s.lam, prior, 0.8, 1e-3, 0)
+    assert info.iters == 0 and np.all(x == 0.0)
+    x, info = sysm.solve(s.y, s.lam, prior, 0.8, 1e-3, 0, tol=1e-3)
+    assert info.iters == 0 and info.status == m.MACE_W_MAXITER
+    xv, iv = sysm.solve_volume(np.stack([s.y, s.y]), np.stack([s.lam, s.lam]), prior, 0.5, 0.8,
+                               1e-3, 0, tol=1e-3)
+    assert iv.iters == 0 and iv.status == m.MACE_W_MAXITER and np.all(xv == 0.0)

@@ -99,6 +99,24 @@ def test_noalloc_warm_start_and_tolerance(m):
     assert np.array_equal(xa, xb)
 
 
+def test_noalloc_zero_iterations(m):
+    """max_iters = 0: both entry points return mean_i w_init with no
+    iteration counted, and MACE_W_MAXITER when a tolerance is set."""
+    g = mi.Geometry(24, 24, 40, 32)
+    cp, row, val = mi.system_matrix(g)
+    s = mi.scan(g, 36)
+    N = 2
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N)
+    prior = m.make_prior(0, 0.002)
+    w0 = np.random.default_rng(2).uniform(0.0, 0.03, N * g.n).astype(np.float32)
+    xa, ia, xb, ib = _both(m, sysm, s, prior, 1e-3, 0, w0=w0)
+    assert np.array_equal(xa, xb)
+    assert ia.iters == ib.iters == 0 and ia.status == ib.status == m.MACE_OK
+    xa, ia, xb, ib = _both(m, sysm, s, prior, 1e-3, 0, tol=1e-3)
+    assert ia.status == ib.status == m.MACE_W_MAXITER and np.all(xb == 0.0)
+    sysm.close()
+
+
 def test_noalloc_concurrent_schedule_same_fixed_point(m):
     """Concurrent super-voxels (float atomics: not bit-reproducible); both
     entry points reach the same fixed point within the FP32 tolerance."""
