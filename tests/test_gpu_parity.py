@@ -364,3 +364,33 @@ def test_zero_iterations_return_the_initial_consensus(m):
     xv, iv = sysm.solve_volume(np.stack([s.y, s.y]), np.stack([s.lam, s.lam]), prior, 0.5, 0.8,
                                1e-3, 0, tol=1e-3)
     assert iv.iters == 0 and iv.status == m.MACE_W_MAXITER and np.all(xv == 0.0)
+
+
+TINY_CASES = [
+    # nx, ny, views, channels, agents: every super-voxel ragged, one-pixel-wide images
+    (1, 1, 4, 4, 2), (1, 5, 6, 8, 2), (5, 1, 6, 8, 3), (3, 2, 5, 6, 1), (2, 2, 2, 4, 2),
+]
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+@pytest.mark.parametrize("case", TINY_CASES, ids=lambda c: f"{c[0]}x{c[1]}v{c[2]}c{c[3]}_N{c[4]}")
+def test_tiny_images_match_oracle(m, case, fmt):
+    """Images of one to six pixels (a single ragged super-voxel, neighbours
+    mostly outside the image): the sequential trajectory equals the
+    oracle's, in both record formats."""
+    nx, ny, nv, nc, N = case
+    g = mi.Geometry(nx, ny, nv, nc)
+    (cp, row, val), s, va, O = _setup(g, 400 + nx + 7 * ny, N, 1, 0.002, 1.2)
+    print(f"tiny {g} N={N} format {fmt}", flush=True)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, rows_per_agent=1,
+                    format=fmt)
+    prior = m.make_prior(1, 0.002, 2.0, 1.2, 1.0)
+    x, info = sysm.solve(s.y, s.lam, prior, 0.8, 0.002, 4)
+    w, X = sysm.state()
+    ref = O.mace_solve(0.8, 0.002, 4, order=sysm.visit_order(), mode=oracle.MODE_SURROGATE)
+    scale = np.abs(ref["x"]).max()
+    assert np.all(np.isfinite(x))
+    assert np.abs(X - ref["X"]).max() <= 5e-5 * scale, np.abs(X - ref["X"]).max() / scale
+    assert np.abs(x - ref["x"]).max() <= 5e-5 * scale
+    assert info.iters == 4
+    assert abs(info.residual - ref["resid"][-1]) <= 1e-3 * ref["resid"][-1] + 1e-7
