@@ -63,6 +63,9 @@ SEQ_CASES = [
     (mi.Geometry(24, 24, 4, 8), 2, 0, 0.003, 2.0, 0.003, 8, 4, 1.0),
     # an odd pixel count (399)
     (mi.Geometry(21, 19, 40, 32), 2, 1, 0.003, 1.2, 0.003, 4, 4, 1.0),
+    # many agents of one or two views each (45 and 90 agents on 90 views)
+    (mi.Geometry(32, 32, 90, 48), 45, 1, 0.002, 1.2, 0.002, 8, 3, 1.0),
+    (mi.Geometry(32, 32, 90, 48), 90, 0, 0.002, 2.0, 0.002, 4, 3, 1.0),
 ]
 
 
