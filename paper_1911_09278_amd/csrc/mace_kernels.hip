@@ -56,13 +56,19 @@ hipError_t launch_sv(const SvArgs& a, int mode, int slots, int grid, size_t lds,
 
 // For every active slot (blockIdx.y): wbar[s] = mean_i w[i][s], and the
 // slot's residual r_k = sqrt(num) / sqrt(den > 0 ? den : ||X||^2) from the
-// per-task FP64 partials (NaN when a partial sum is not finite).  The partials are summed in a fixed order whatever
-// the timing: each of the first kEpiRedBlocks blocks sums a fixed chunk and
-// stores its sums after the task partials; the one of those that arrives
-// last (ticket in counter[1]) adds the block sums in block order, stores r_k
-// at iteration k = counter[0] and resets the ticket.
-constexpr int kEpiBlocks = 1024;    // at most this many blocks per slot
-constexpr int kEpiRedBlocks = 64;   // of which this many sum the residual partials
+// per-task FP64 partials (NaN when a partial sum is not finite).  The
+// first blocks average the agents' w; kEpiRedBlocks more blocks, running
+// beside them, sum the partials in a fixed order whatever the timing: each
+// sums a fixed chunk and stores its sums after the task partials, and the
+// one that arrives last (ticket in counter[1]) adds the block sums in block
+// order, stores r_k at iteration k = counter[0] and resets the ticket.
+constexpr int kEpiBlocks = 1024;    // at most this many averaging blocks per slot
+constexpr int kEpiRedBlocks = 64;   // blocks that sum the residual partials
+
+__host__ __device__ inline int epi_mean_blocks(int n) {
+  const int gx = (n + 255) / 256;
+  return gx < kEpiBlocks ? gx : kEpiBlocks;
+}
 
 __device__ __forceinline__ double load_l2(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -101,26 +107,28 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
   const SlotDesc d = slots[blockIdx.y];
   if (!d.active) return;
   const int tid = threadIdx.x;
-  for (int s = blockIdx.x * blockDim.x + tid; s < n; s += gridDim.x * blockDim.x) {
-    // eight agents' loads in flight before they are added, in agent order
-    float m = 0.0f;
-    int i = 0;
-    for (; i + 8 <= N; i += 8) {
-      float v[8];
+  const int gm = epi_mean_blocks(n);
+  if ((int)blockIdx.x < gm) {  // an averaging block
+    for (int s = blockIdx.x * blockDim.x + tid; s < n; s += gm * blockDim.x) {
+      // eight agents' loads in flight before they are added, in agent order
+      float m = 0.0f;
+      int i = 0;
+      for (; i + 8 <= N; i += 8) {
+        float v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = d.w[(size_t)(i + u) * n + s];
+        for (int u = 0; u < 8; ++u) v[u] = d.w[(size_t)(i + u) * n + s];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) m += v[u];
+        for (int u = 0; u < 8; ++u) m += v[u];
+      }
+      for (; i < N; ++i) m += d.w[(size_t)i * n + s];
+      d.wbar[s] = m / (float)N;
     }
-    for (; i < N; ++i) m += d.w[(size_t)i * n + s];
-    d.wbar[s] = m / (float)N;
+    return;
   }
-  // this block's fixed chunk of the task partials (the first kEpiRedBlocks
-  // blocks only, so that few blocks take a ticket)
-  const int nb = min((int)gridDim.x, kEpiRedBlocks);
-  if ((int)blockIdx.x >= nb) return;
+  // a reduction block: its fixed chunk of the task partials
+  const int nb = kEpiRedBlocks, rb = (int)blockIdx.x - gm;
   const int chunk = (nparts + nb - 1) / nb;
-  const int p0 = blockIdx.x * chunk, p1 = min(nparts, p0 + chunk);
+  const int p0 = rb * chunk, p1 = min(nparts, p0 + chunk);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int p = p0 + tid; p < p1; p += 256) {
     s0 += d.part[(size_t)p * 4 + 0];
@@ -132,9 +140,9 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
   block_sum3(s0, s1, s2, bs);
   double* bpart = d.part + (size_t)nparts * 4;
   if (tid == 0) {
-    bpart[blockIdx.x * 4 + 0] = bs[0];
-    bpart[blockIdx.x * 4 + 1] = bs[1];
-    bpart[blockIdx.x * 4 + 2] = bs[2];
+    bpart[rb * 4 + 0] = bs[0];
+    bpart[rb * 4 + 1] = bs[1];
+    bpart[rb * 4 + 2] = bs[2];
     __threadfence();
     last = atomicAdd(&d.counter[1], 1) == nb - 1;
   }
@@ -170,8 +178,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
 hipError_t launch_epilogue(const SlotDesc* slots, int n_slots, int N, int n, int nparts,
                            hipStream_t st, double* sums) {
   if (n_slots <= 0) return hipSuccess;
-  int gx = (n + 255) / 256;
-  if (gx > kEpiBlocks) gx = kEpiBlocks;
+  const int gx = epi_mean_blocks(n) + kEpiRedBlocks;
   hipLaunchKernelGGL(epilogue_kernel, dim3(gx, n_slots), dim3(256), 0, st, slots, N, n, nparts,
                      sums);
   return hipGetLastError();
