@@ -110,9 +110,17 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
   const int gm = epi_mean_blocks(n);
   if ((int)blockIdx.x < gm) {  // an averaging block
     for (int s = blockIdx.x * blockDim.x + tid; s < n; s += gm * blockDim.x) {
-      // eight agents' loads in flight before they are added, in agent order
+      // sixteen (then eight) agents' loads in flight before they are added,
+      // in agent order
       float m = 0.0f;
       int i = 0;
+      for (; i + 16 <= N; i += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = d.w[(size_t)(i + u) * n + s];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) m += v[u];
+      }
       for (; i + 8 <= N; i += 8) {
         float v[8];
 #pragma unroll
@@ -130,6 +138,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const SlotDesc* __restric
   const int chunk = (nparts + nb - 1) / nb;
   const int p0 = rb * chunk, p1 = min(nparts, p0 + chunk);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
   for (int p = p0 + tid; p < p1; p += 256) {
     s0 += d.part[(size_t)p * 4 + 0];
     s1 += d.part[(size_t)p * 4 + 1];
