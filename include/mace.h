@@ -212,6 +212,20 @@ int mace_solve_volume(mace_system* sys, int32_t nz, const float* y, const float*
                       mace_info* info);
 
 /*
+ * Super-voxel groups of a volume (SV-ICD's multi-slice super-voxels, Sec. IV:
+ * the slices of a group are swept together per super-voxel): with slices = G
+ * > 1, mace_solve_volume takes the slices in groups of G consecutive ones;
+ * one row of the sweep takes a super-voxel of one agent through the G slices
+ * of its group in turn (slice z sees slice z - 1's new values of the same
+ * pass), and the even / odd groups sweep in separate launches, so a group's
+ * axial neighbours in the next group hold still while it runs.  G = 1
+ * (default) is the even / odd slice scheme.  The fixed point does not depend
+ * on G (only the visiting order changes).  slices in [1, 128]; applies to
+ * later mace_solve_volume calls.
+ */
+int mace_set_slice_group(mace_system* sys, int32_t slices);
+
+/*
  * Partial-update MACE with a plug-and-play prior (Algorithm 3, Sec. III):
  * the agents apply partial updates of the proximal maps of their data terms
  * alone (beta = 0, no prior), F_i(v; sqrt(N) sigma) (eq. (FG_PnP)), and the

@@ -110,6 +110,8 @@ def _load():
     L.mace_get_error_sinogram.restype = ctypes.c_int
     L.mace_set_relaxation.argtypes = [vp, d]
     L.mace_set_relaxation.restype = ctypes.c_int
+    L.mace_set_slice_group.argtypes = [vp, i32]
+    L.mace_set_slice_group.restype = ctypes.c_int
     L.mace_set_fp32_tail.argtypes = [vp, i32]
     L.mace_set_fp32_tail.restype = ctypes.c_int
     L.mace_set_timing.argtypes = [vp, i32]
@@ -158,7 +160,7 @@ EXPORTED = ("mace_load_system", "mace_solve", "mace_solve_pnp", "mace_solve_dev"
             "mace_free_system", "mace_last_error", "mace_test_fail_alloc",
             "mace_solve_dev_noalloc", "mace_noalloc_capacity", "mace_set_fp32_tail",
             "mace_solve_resume", "mace_server_cancel", "mace_solve_volume",
-            "mace_get_slot_state")
+            "mace_get_slot_state", "mace_set_slice_group")
 
 
 def noalloc_capacity() -> int:
@@ -438,6 +440,11 @@ class System:
 
     def set_relaxation(self, gamma):
         _check(_lib.mace_set_relaxation(self._h, float(gamma)))
+
+    def set_slice_group(self, slices):
+        """Consecutive slices per super-voxel group of later volume solves
+        (see mace_set_slice_group)."""
+        _check(_lib.mace_set_slice_group(self._h, int(slices)))
 
     def set_fp32_tail(self, iters):
         """FP32 tail of later solves (precision-1 systems; see mace_opts)."""

@@ -587,8 +587,18 @@ struct HostSchedule {
 // placed in workgroups of XCD a mod 8, so the agent's sinogram blocks and its
 // matrix records stay in one L2; all slots walk the SVs in the same order, so
 // the same records are read by several slots at about the same time.
+// Slot sl takes part in a schedule of this parity (-1: every slot; else the
+// slots whose group of `group` consecutive slots has that parity -- the
+// even / odd slices of a volume, or its even / odd slice groups).
+static bool slot_in(int sl, int parity, int group) {
+  return parity < 0 || ((sl / group) & 1) == parity;
+}
+
+// group > 1 (a volume's slice groups): a row holds one group of that many
+// consecutive slots for one (agent, rank) and sweeps each of its super-voxels
+// through the group's slices in order before the next super-voxel.
 static void build_schedule(const mace_system* s, int n_slots, int only_agent, int P, int parity,
-                           HostSchedule& hs) {
+                           int group, HostSchedule& hs) {
   std::vector<int> agents;
   if (only_agent >= 0)
     agents.push_back(only_agent);
@@ -603,9 +613,10 @@ static void build_schedule(const mace_system* s, int n_slots, int only_agent, in
   // hold the same rank of every slot and agent, so the slots of a batch
   // walk the super-voxels in step and share the matrix records in L2
   // (parity 0 / 1: only the even / odd slots -- the slices of a volume)
+  // (with slice groups, a row's slot is its group's first slot)
   for (int r = 0; r < P; ++r)
-    for (int sl = 0; sl < n_slots; ++sl) {
-      if (parity >= 0 && (sl & 1) != parity) continue;
+    for (int sl = 0; sl < n_slots; sl += group) {
+      if (!slot_in(sl, parity, group)) continue;
       for (size_t i = 0; i < agents.size(); ++i) xrows[agents[i] % nxcd].push_back({sl, agents[i], r});
     }
   int wg_per_xcd = 0, used = 0;
@@ -633,16 +644,19 @@ static void build_schedule(const mace_system* s, int n_slots, int only_agent, in
   hs.R = hs.grid * s->rpb;
   for (int c = 0; c < 4; ++c) {
     const auto& L = s->colour_svs[c];
-    const int T = (int)((L.size() + P - 1) / P);
+    const int Tsv = (int)((L.size() + P - 1) / P);  // super-voxels per row
+    const int T = Tsv * group;
     hs.T[c] = T;
     hs.tab[c].assign((size_t)hs.R * std::max(T, 1), -1);
     for (int r = 0; r < hs.R; ++r) {
       const RowId id = row_of[r];
       if (id.agent < 0) continue;
-      for (int t = 0; t < T; ++t) {
+      for (int t = 0; t < Tsv; ++t) {
         const size_t q = (size_t)t * P + id.rank;
-        if (q < L.size())
-          hs.tab[c][(size_t)r * T + t] = (id.slot << kSlotShift) | (id.agent * s->n_sv + L[q]);
+        if (q >= L.size()) continue;
+        for (int z = 0; z < group && id.slot + z < n_slots; ++z)
+          hs.tab[c][(size_t)r * T + (size_t)t * group + z] =
+              ((id.slot + z) << kSlotShift) | (id.agent * s->n_sv + L[q]);
       }
     }
   }
@@ -651,7 +665,7 @@ static void build_schedule(const mace_system* s, int n_slots, int only_agent, in
 // Every (slot, agent, SV) of the scheduled agents and slots appears exactly
 // once per pass, in the phase of its colour, and every task id is in range.
 static int check_schedule(const mace_system* s, int n_slots, int only_agent, int parity,
-                          const HostSchedule& hs) {
+                          int group, const HostSchedule& hs) {
   const size_t per_slot = (size_t)s->N * s->n_sv;
   if (per_slot >= ((size_t)1 << kSlotShift)) return fail(MACE_E_ARG, "check: too many (agent, SV) pairs");
   if (n_slots > kMaxScanSlots) return fail(MACE_E_ARG, "check: too many slots");
@@ -668,7 +682,7 @@ static int check_schedule(const mace_system* s, int n_slots, int only_agent, int
   for (int sl = 0; sl < n_slots; ++sl)
     for (int a = 0; a < s->N; ++a)
       for (int sv = 0; sv < s->n_sv; ++sv) {
-        const int want = (only_agent < 0 || only_agent == a) && (parity < 0 || (sl & 1) == parity) ? 1 : 0;
+        const int want = (only_agent < 0 || only_agent == a) && slot_in(sl, parity, group) ? 1 : 0;
         const int got = seen[(size_t)sl * per_slot + (size_t)a * s->n_sv + sv];
         if (got != want) return fail(MACE_E_ARG, "check: task visited %d times", got);
       }
@@ -676,13 +690,13 @@ static int check_schedule(const mace_system* s, int n_slots, int only_agent, int
 }
 
 namespace mace {
-Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P, int parity) {
-  const auto key = std::make_tuple(n_slots, only_agent, P, parity);
+Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P, int parity, int group) {
+  const auto key = std::make_tuple(n_slots, only_agent, P, parity, group);
   auto it = s->schedules.find(key);
   if (it != s->schedules.end()) return it->second.get();
   HostSchedule hs;
-  build_schedule(s, n_slots, only_agent, P, parity, hs);
-  if (check_schedule(s, n_slots, only_agent, parity, hs)) return nullptr;
+  build_schedule(s, n_slots, only_agent, P, parity, group, hs);
+  if (check_schedule(s, n_slots, only_agent, parity, group, hs)) return nullptr;
   auto sch = std::make_unique<Schedule>();
   sch->grid = hs.grid;
   sch->R = hs.R;
@@ -919,12 +933,14 @@ extern "C" int mace_check_layout(const mace_geom* geom, const int64_t* col_ptr,
   for (int only = -1; only < s.N; ++only) {
     for (int PP : {1, P}) {
       for (int ns : {1, 3})
-        for (int par : {-1, 0, 1}) {  // all slots; the even / odd slices of a volume
-          HostSchedule hs;
-          build_schedule(&s, ns, only, PP, par, hs);
-          rc = check_schedule(&s, ns, only, par, hs);
-          if (rc) return rc;
-        }
+        for (int par : {-1, 0, 1})  // all slots; the even / odd slices (groups) of a volume
+          for (int grp : {1, 2}) {
+            if (par < 0 && grp > 1) continue;
+            HostSchedule hs;
+            build_schedule(&s, ns, only, PP, par, grp, hs);
+            rc = check_schedule(&s, ns, only, par, grp, hs);
+            if (rc) return rc;
+          }
     }
     if (only >= 2) break;
   }
@@ -952,6 +968,14 @@ extern "C" int mace_set_relaxation(mace_system* s, double relax) {
   if (!s) return fail(MACE_E_ARG, "NULL system");
   if (!(relax > 0.0 && relax <= 1.0)) return fail(MACE_E_ARG, "relaxation must be in (0, 1]");
   s->relax = relax;
+  return MACE_OK;
+}
+
+extern "C" int mace_set_slice_group(mace_system* s, int32_t slices) {
+  if (!s) return fail(MACE_E_ARG, "NULL system");
+  if (slices < 1 || slices > kMaxScanSlots)
+    return fail(MACE_E_ARG, "slices per group must be in [1, %d]", kMaxScanSlots);
+  s->slice_group = slices;
   return MACE_OK;
 }
 

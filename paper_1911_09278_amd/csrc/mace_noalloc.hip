@@ -152,7 +152,7 @@ extern "C" int mace_solve_dev_noalloc(mace_system* s, const float* y, const floa
                 L.bytes, kScratchBytes);
   // the one-slot schedule of the automatic rows per agent, built at load
   const int P = default_rows_per_agent(s);
-  auto it = s->schedules.find(std::make_tuple(1, -1, P, -1));
+  auto it = s->schedules.find(std::make_tuple(1, -1, P, -1, 1));
   if (it == s->schedules.end() || !it->second)
     return fail(MACE_E_HIP, "the system's one-scan schedule is missing");
   const Schedule* sch = it->second.get();

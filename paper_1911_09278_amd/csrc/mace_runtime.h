@@ -155,7 +155,8 @@ struct mace_system {
   mace::DevBuf<int> band_rows;
   mace::DevBuf<int> d_sv_pix0;
   mace::DevBuf<int> row_src;  // agent-block row -> global row (or -1)
-  std::map<std::tuple<int, int, int, int>, std::unique_ptr<mace::Schedule>> schedules;
+  // key: (slots, only agent, rows per agent, parity, slice group)
+  std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<mace::Schedule>> schedules;
   // slot 0 serves mace_solve / mace_prox; mace_solve_batch uses 0..B-1
   mace::Batch batch;
   hipStream_t stream = nullptr;
@@ -163,6 +164,7 @@ struct mace_system {
   int64_t matrix_bytes = 0;
   bool timing = false;
   double relax = 0.0;  // 0: automatic (1 for the sequential schedule, 0.5 otherwise)
+  int slice_group = 1;  // volumes: consecutive slices per super-voxel group
   std::vector<hipEvent_t> ev;
   ~mace_system();
 };
@@ -170,7 +172,8 @@ struct mace_system {
 namespace mace {
 int default_rows_per_agent(const mace_system* s);
 // Task tables for n_slots slots (parity 0 / 1: only the even / odd slots).
-Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P, int parity = -1);
+Schedule* get_schedule(mace_system* s, int n_slots, int only_agent, int P, int parity = -1,
+                       int group = 1);
 int check_prior(const mace_prior* pr);
 void fill_args(const mace_system* s, SvArgs& a, const mace_prior* pr, double rho, double sigma,
                bool fp16);

@@ -496,18 +496,23 @@ int solve_volume_impl(mace_system* s, int nz, const float* y, const float* lam,
   if (max_iters < 0) return fail(MACE_E_ARG, "max_iters must be >= 0");
   Batch& b = s->batch;
   hipStream_t st = s->stream;
-  // rows per agent for the slices of one parity together
-  const int P = batch_rows_per_agent(s, (nz + 1) / 2, false);
-  const Schedule* sch[2] = {get_schedule(s, nz, -1, P, 0),
-                            nz > 1 ? get_schedule(s, nz, -1, P, 1) : nullptr};
-  if (!sch[0] || (nz > 1 && !sch[1])) return fail(MACE_E_HIP, "schedule upload failed");
+  // slices in groups of Z (1: each slice its own group); rows per agent
+  // for the groups of one parity together
+  const int Z = std::max(1, std::min(s->slice_group, nz));
+  const int ngroups = (nz + Z - 1) / Z;
+  const int P = batch_rows_per_agent(s, (ngroups + 1) / 2, false);
+  const Schedule* sch[2] = {get_schedule(s, nz, -1, P, 0, Z),
+                            ngroups > 1 ? get_schedule(s, nz, -1, P, 1, Z) : nullptr};
+  if (!sch[0] || (ngroups > 1 && !sch[1])) return fail(MACE_E_HIP, "schedule upload failed");
   for (int z = 0; z < nz; ++z) {
     rc = ensure_slot(s, b, z, max_iters);
     if (rc) return rc;
   }
   SvArgs a;
   fill_args(s, a, pr, rho, sigma, false);
-  a.strict = P == 1 ? 1 : 0;
+  // a row sweeps a super-voxel through its group's slices in turn: each
+  // task's stores complete before the next reads its axial neighbours
+  a.strict = (P == 1 || Z > 1) ? 1 : 0;
   a.vol_nz = nz;
   a.baxial = (float)b_axial;
   const size_t m = (size_t)s->n_views * s->n_ch;

@@ -395,6 +395,8 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
     const bool has_lo = VOL && cur.slot > 0, has_hi = VOL && cur.slot + 1 < a.vol_nz;
     const int zn = lr == 9 ? (has_lo ? cur.slot - 1 : cur.slot)
                            : (lr == 10 && has_hi ? cur.slot + 1 : cur.slot);
+    // (read at agent scope, past the L1: with slice groups the row itself
+    // updated slice z - 1 in its previous task)
     gptr<const float> axp = nullptr;
     if constexpr (VOL) axp = glb((const float*)a.slots[zn].X) + img;
     const float ax_in = (lr == 9 ? has_lo : has_hi) ? 1.0f : 0.0f;
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
 #pragma unroll
       for (int q = 0; q < kPrefetch; ++q) {
         load_rec_at<SL, F16>(vb, hb, sb, db, kstr, last_ok, lr, q, buf[q]);
-        if constexpr (VOL) buf[q].ax = axp[(size_t)(y0 + q / S) * a.nx + x0 + q % S];
+        if constexpr (VOL) buf[q].ax = load_e(axp + (size_t)(y0 + q / S) * a.nx + x0 + q % S);
       }
 #pragma unroll
       for (int j = 0; j < S * S; ++j) {
@@ -499,7 +501,7 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
           load_rec_at<SL, F16>(vb, hb, sb, db, kstr, last_ok, lr, j + kPrefetch, buf[j + kPrefetch]);
           if constexpr (VOL) {
             const int q = j + kPrefetch;
-            buf[q].ax = axp[(size_t)(y0 + q / S) * a.nx + x0 + q % S];
+            buf[q].ax = load_e(axp + (size_t)(y0 + q / S) * a.nx + x0 + q % S);
           }
         }
         update(buf[j], j, j / S, j % S);
@@ -509,7 +511,7 @@ __global__ __launch_bounds__(kBlockThreads, Occupancy<SL>::waves) void sv_kernel
       for (int j = 0; j < npix; ++j) {
         Rec<SL> cur;
         load_rec<SL, F16>(a, rec0 + j, lr, cur);
-        if constexpr (VOL) cur.ax = axp[(size_t)(y0 + j / sw) * a.nx + x0 + j - (j / sw) * sw];
+        if constexpr (VOL) cur.ax = load_e(axp + (size_t)(y0 + j / sw) * a.nx + x0 + j - (j / sw) * sw);
         update(cur, j, j / sw, j - (j / sw) * sw);
       }
     }

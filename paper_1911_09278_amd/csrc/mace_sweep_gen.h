@@ -259,8 +259,10 @@ __global__ __launch_bounds__(kBlockThreads) void sv_kernel_gen(SvArgs a) {
         vv[p] = 2.0f * cwbar[pix] - cw[img + pix];
         t2[p] = cth2[img + pix];
         if (a.vol_nz > 0) {
-          xlo[p] = has_lo ? Xlo[img + pix] : 0.0f;
-          xhi[p] = has_hi ? Xhi[img + pix] : 0.0f;
+          // agent scope, past the L1: with slice groups the row itself
+          // updated slice z - 1 in its previous task
+          xlo[p] = has_lo ? load_e(Xlo + img + pix) : 0.0f;
+          xhi[p] = has_hi ? load_e(Xhi + img + pix) : 0.0f;
         }
       }
     }

@@ -207,3 +207,82 @@ def test_volume_slice_count_out_of_range(m):
                                       0.002, 1, 2, 0.0, p(x), ctypes.byref(info))
         assert rc == m.MACE_E_ARG, (nz, rc)
         assert "nz must be in [1, 128]" in m.last_error()
+
+
+def _group_order(sysm, g, nz, S, Z):
+    """The GPU's sequential visiting order with slice groups of Z: colour c,
+    then the even groups, then the odd ones; inside a group each
+    super-voxel (in the 2-D visiting order) through the group's slices in
+    turn, raster order inside."""
+    o2 = sysm.visit_order()
+    col = ((o2 % g.nx) // S & 1) + 2 * ((o2 // g.nx) // S & 1)
+    gx = (g.nx + S - 1) // S
+    svid = (o2 // g.nx // S) * gx + (o2 % g.nx) // S
+    ngroups = (nz + Z - 1) // Z
+    out = []
+    for c in range(4):
+        part, sv = o2[col == c], svid[col == c]
+        runs = np.split(part, np.flatnonzero(np.diff(sv)) + 1)
+        for par in (0, 1):
+            for gi in range(par, ngroups, 2):
+                for run in runs:
+                    for z in range(gi * Z, min(nz, (gi + 1) * Z)):
+                        out.append(z * g.n + run)
+    return np.concatenate(out)
+
+
+GROUP_CASES = [
+    # geometry, nz, N, prior kind, sigma_x, q, b_axial, sigma, S, iterations, format, slices per group
+    (mi.Geometry(24, 24, 24, 36), 4, 2, 1, 0.002, 1.2, 0.5, 0.001, 8, 3, 1, 2),
+    (mi.Geometry(20, 18, 30, 30), 7, 3, 0, 0.003, 2.0, 0.25, 0.002, 4, 3, 1, 3),   # ragged last group
+    (mi.Geometry(24, 24, 24, 36), 4, 2, 1, 0.002, 1.2, 0.5, 0.001, 8, 3, 2, 2),
+    (mi.Geometry(20, 18, 30, 30), 5, 3, 0, 0.003, 2.0, 1.0, 0.002, 4, 3, 2, 8),   # one group
+]
+
+
+@pytest.mark.parametrize("case", GROUP_CASES,
+                         ids=lambda c: f"{c[0].nx}x{c[0].ny}z{c[1]}_N{c[2]}_S{c[8]}_f{c[10]}_G{c[11]}")
+def test_slice_groups_sequential_trajectory_matches_oracle(m, case):
+    g, nz, N, kind, sx, q, ba, sigma, S, iters, fmt, Z = case
+    (cp, row, val), y, lam, O = _volume(g, nz, 501 + g.nx, N, kind, sx, ba, q)
+    print(f"slice groups of {Z}: {g} nz={nz} N={N} S={S} format={fmt}", flush=True)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, sv_size=S,
+                    rows_per_agent=1, format=fmt)
+    sysm.set_slice_group(Z)
+    prior = m.make_prior(kind, sx, 2.0, q, 1.0)
+    x, info = sysm.solve_volume(y, lam, prior, ba, 0.8, sigma, iters)
+    order = _group_order(sysm, g, nz, S, Z)
+    assert np.array_equal(np.sort(order), np.arange(nz * g.n))
+    ref = O.mace_solve(0.8, sigma, iters, order=order, mode=oracle.MODE_SURROGATE)
+    scale = np.abs(ref["x"]).max()
+    assert np.all(np.isfinite(x))
+    assert np.abs(x.reshape(-1) - ref["x"]).max() <= 5e-5 * scale
+    for z in range(nz):
+        _, Xz = sysm.slot_state(z)
+        err = np.abs(Xz - ref["X"][:, z * g.n:(z + 1) * g.n]).max()
+        assert err <= 5e-5 * scale, (z, err / scale)
+    assert abs(info.residual - ref["resid"][-1]) <= 1e-3 * ref["resid"][-1] + 1e-7
+
+
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_slice_groups_concurrent_fixed_point_is_the_map(m, volume_map, fmt):
+    g, nz, N, sx, ba, (cp, row, val), y, lam, xmap = volume_map
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, N, format=fmt)
+    sysm.set_relaxation(0.5)
+    sysm.set_slice_group(2)
+    x, info = sysm.solve_volume(y, lam, m.make_prior(0, sx), ba, 0.8, 5e-4, 20000, tol=1e-7)
+    e = float(np.linalg.norm(x.reshape(-1).astype(np.float64) - xmap) / np.linalg.norm(xmap))
+    print(f"slice groups of 2, format {fmt}: {info.iters} iterations, r {info.residual:.2e}, "
+          f"nrmse {e:.2e}", flush=True)
+    assert info.status == m.MACE_OK
+    assert e <= 1e-4
+
+
+def test_slice_group_argument_errors(m):
+    g = mi.Geometry(16, 16, 8, 24)
+    cp, row, val = mi.system_matrix(g)
+    sysm = m.System(g.nx, g.ny, g.n_views, g.n_channels, cp, row, val, 2)
+    for bad in (0, -2, 129):
+        with pytest.raises(m.MaceError) as ei:
+            sysm.set_slice_group(bad)
+        assert ei.value.code == m.MACE_E_ARG
