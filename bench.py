@@ -342,8 +342,9 @@ def leg_volume(m, mi, torch, iters=60, nz=16, b_axial=0.5):
     q-GGMRF) with the 3-D prior's axial cliques (b_axial = 0.5 against the
     in-plane weights' sum of 1), `iters` Mann iterations through
     mace_solve_volume (host arrays in and out), with the compact and with
-    the general records, against the same 16 slices solved as an independent
-    batch (mace_solve_batch) with the same records."""
+    the general records, also with super-voxels in groups of 8 slices,
+    against the same 16 slices solved as an independent batch
+    (mace_solve_batch) with the same records."""
     w = mi.WORKLOADS["serve256"]
     g = w.geom
     sigma = 2e-4
@@ -371,8 +372,16 @@ def leg_volume(m, mi, torch, iters=60, nz=16, b_axial=0.5):
         t0 = time.perf_counter()
         infos = sysm.solve_batch(list(y), list(lam), prior, w.rho, sigma, iters)[1]
         tb = time.perf_counter() - t0
+        # super-voxels in groups of 8 slices (SV-ICD's slice groups)
+        sysm.set_slice_group(8)
+        sysm.solve_volume(y, lam, prior, b_axial, w.rho, sigma, 2)
+        t0 = time.perf_counter()
+        _, info8 = sysm.solve_volume(y, lam, prior, b_axial, w.rho, sigma, iters)
+        tg = time.perf_counter() - t0
         out[name] = {"volume_ms_per_mann_iter": tv / iters * 1e3, "volume_residual": info.residual,
                      "volume_voxel_updates_per_s": iters * w.n_agents * g.n * nz / tv,
+                     "groups8_ms_per_mann_iter": tg / iters * 1e3,
+                     "groups8_residual": info8.residual,
                      "batch_ms_per_mann_iter": tb / iters * 1e3,
                      "batch_mean_residual": float(np.mean([i.residual for i in infos]))}
         sysm.close()
